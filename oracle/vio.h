@@ -1,0 +1,123 @@
+/* vio.h -- CPU oracle for the global patch-based video inpainting of
+ * Newson, Almansa, Fradet, Gousseau, Perez, "Video Inpainting of Complex
+ * Scenes" (SIAM J. Imaging Sciences 2014, arXiv 1503.05528).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the plain, slow, obviously correct
+ * reference that the HIP library is checked against.  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg may load it; the
+ * product path never calls it.  It shares no code with the HIP library.
+ *
+ * All pointers are HOST pointers.  Every function returns vio_status
+ * (0 = OK, < 0 = error) unless stated otherwise.
+ *
+ * Conventions (the paper is silent on them; readings listed in the design
+ * notes):
+ *   position p = (x, y, t), 0-based, lin(p) = (t*H + y)*W + x;
+ *   level 0 is the finest, level L-1 the coarsest;
+ *   patch offsets o are enumerated dt-major, then dy, then dx, each
+ *   ascending from -h to +h;
+ *   colour and texture channels are 0..255 integers (uint8);
+ *   a voxel carries 5 channels R, G, B, Tx, Ty.
+ */
+#ifndef VIO_H
+#define VIO_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  VIO_OK = 0,
+  VIO_E_INVAL = -1,
+  VIO_E_NOMEM = -2,
+  VIO_E_STATE = -4,
+  VIO_E_EMPTY_SOURCE = -5
+};
+enum { VIO_RECON_WEIGHTED = 0, VIO_RECON_MEAN = 1, VIO_RECON_BEST = 2 };
+
+typedef struct {
+  int32_t abi_version;  /* 1 */
+  int32_t patch[3];     /* patch size (x, y, t), odd; 5x5x5 (Sec. 3.7) */
+  int32_t levels;       /* pyramid levels L >= 1 */
+  int32_t lambda;       /* texture weight, 50 (Sec. 3.7) */
+  int32_t pm_iters;     /* PatchMatch iterations, 10 (Sec. 3.1, 3.7) */
+  int32_t n_jf;         /* propagation steps per iteration */
+  int32_t jf_steps[8];  /* {4, 2, 1} */
+  double rho;           /* random-search window reduction, 0.5 (Eq. 3.1 of Sec. 3.1) */
+  int32_t em_max_iters; /* 20 (Sec. 3.7) */
+  double em_tol;        /* 0.1, mean absolute colour change; < 0: run em_max_iters */
+  int32_t recon_mode;   /* VIO_RECON_WEIGHTED or VIO_RECON_MEAN */
+  uint64_t seed;        /* Philox key word 0 */
+} vio_params;
+
+typedef struct vio_ctx vio_ctx;
+
+int vio_params_default(vio_params* out);
+
+/* Builds the image, occlusion and texture-feature pyramids and the source /
+ * target sets of every level.  rgb [T][H][W][3], mask [T][H][W] (1 = hole);
+ * rgb values under the mask are never read. */
+int vio_create(vio_ctx** out, const vio_params* prm, int32_t W, int32_t H, int32_t T,
+               const uint8_t* rgb, const uint8_t* mask);
+void vio_destroy(vio_ctx* ctx);
+
+/* dims[3] = (W_l, H_l, T); counts[3] = (|H^l|, |H~^l|, |D~^l|) */
+int vio_level_info(const vio_ctx* ctx, int32_t level, int32_t dims[3], int64_t counts[3]);
+/* byte masks over the level volume: hole H^l, sources D~^l, targets H~^l */
+int vio_level_sets(const vio_ctx* ctx, int32_t level, uint8_t* hole, uint8_t* dsrc,
+                   uint8_t* htil);
+
+/* State of a level.  rgbt [V][5]; cand [V] absolute linear index (-1 unset or
+ * outside H~); dist [V] integer SSD (-1 outside H~); nvox [V] number of
+ * voxels the SSD counted (0 outside H~).  NULL pointers are skipped. */
+int vio_get_state(const vio_ctx* ctx, int32_t level, uint8_t* rgbt, int32_t* cand,
+                  int32_t* dist, uint8_t* nvox);
+int vio_set_state(vio_ctx* ctx, int32_t level, const uint8_t* rgbt, const int32_t* cand,
+                  const int32_t* dist, const uint8_t* nvox);
+
+/* Integer SSD between the patches centred at p and at c (linear indices) at
+ * a level; count_mask (or NULL for all) selects the compared voxels p+o. */
+int64_t vio_patch_ssd(const vio_ctx* ctx, int32_t level, int64_t p, int64_t c,
+                      const uint8_t* count_mask, int32_t* n_out);
+
+/* Philox4x64-10 block: out = Philox(counter, key). */
+void vio_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* ANN search (Alg. "ANN search with 3D PatchMatch", redesigned as
+ * synchronous propagation) over the target set H~^level with the full
+ * distance; em_iter keys the random numbers. */
+int vio_nnf_search(vio_ctx* ctx, int32_t level, int32_t em_iter);
+/* The same search over an arbitrary target set and comparison mask
+ * (count_mask NULL = all voxels); step keys the random numbers. */
+int vio_nnf_search_set(vio_ctx* ctx, int32_t level, const uint8_t* target_mask,
+                       const uint8_t* count_mask, uint64_t step);
+
+/* Reconstruction of the hole H^level (Eqs. of Sec. 3.2).  out_f, if not NULL,
+ * receives [|H^l|][5] values in [0,1] in ascending linear order of the hole;
+ * absdiff, if not NULL, receives sum over the hole of |new - old| over RGB. */
+int vio_reconstruct(vio_ctx* ctx, int32_t level, int32_t mode, float* out_f, int64_t* absdiff);
+
+/* One pyramid level of the EM loop (Alg. "Proposed video inpainting
+ * algorithm", inner while loop); iters_run receives the number of
+ * iterations. */
+int vio_inpaint_level(vio_ctx* ctx, int32_t level, int32_t* iters_run);
+/* Onion-peel initialisation at the coarsest level (Sec. 3.5). */
+int vio_onion_init(vio_ctx* ctx, int32_t* layers_run);
+/* Level transition level+1 -> level: nearest-neighbour upsampling of the
+ * shift map, then reconstruction of the finer hole (Sec. 3.6). */
+int vio_transition(vio_ctx* ctx, int32_t level);
+/* The whole method minus realignment: out_rgb [T][H][W][3]. */
+int vio_inpaint(vio_ctx* ctx, uint8_t* out_rgb);
+
+/* E = sum over H~^level of SSD(q, cand(q)) (unnormalised). */
+int64_t vio_energy(const vio_ctx* ctx, int32_t level);
+
+/* number of OpenMP threads the oracle uses (1 without OpenMP) */
+int vio_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
