@@ -1,0 +1,207 @@
+/* vi.h -- C ABI of libvi, the MI355X (gfx950) implementation of the hot path
+ * of Newson, Almansa, Fradet, Gousseau, Perez, "Video Inpainting of Complex
+ * Scenes" (SIAM J. Imaging Sciences 7(4), 2014; arXiv 1503.05528).
+ *
+ * The problem (Sec. 2): a colour video u over a space-time volume Omega and
+ * an occlusion H (a set of positions) are given; the method fills u on H by
+ * alternating an approximate-nearest-neighbour search of a shift map phi over
+ * 5x5x5 patches (Sec. 3.1) and a reconstruction of every occluded pixel from
+ * the patches that cover it (Sec. 3.2), inside a multi-resolution pyramid
+ * with texture features (Sec. 3.3, 3.6) and an onion-peel initialisation
+ * (Sec. 3.5); the complete loop is Alg. 4.  Affine realignment (Sec. 3.4) is
+ * not part of this library.
+ *
+ * Conventions
+ *   - Every function returns vi_status (VI_OK = 0, negative = error) unless
+ *     stated otherwise; no C++ exception crosses the ABI; vi_last_error()
+ *     returns a thread-local message for the last failing call.
+ *   - (dev) marks device pointers (memory of the GPU the context was created
+ *     on, e.g. a torch tensor's data_ptr()); (host) marks host pointers.
+ *   - All device work is enqueued on the context's HIP stream; a call returns
+ *     after enqueueing unless marked "syncs".  The caller owns every buffer
+ *     it passes; the context owns everything it allocates.
+ *   - Positions p = (x, y, t) are 0-based; linear index lin(p) =
+ *     (t*H_l + y)*W_l + x at level l; level 0 is the finest.
+ *   - Colour and texture channels are integers 0..255; a voxel carries five
+ *     channels R, G, B, Tx, Ty.
+ *   - Limits: W < 32768, H < 32768, T < 32768, W*H*T < 2^31, levels <= 12,
+ *     patch = 5x5x5, 1 <= jump-flood step <= 4, lambda <= 130 (keeps the
+ *     integer distance below 2^31).
+ */
+#ifndef VI_H
+#define VI_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VI_OK = 0,
+  VI_E_INVAL = -1,        /* bad argument (null pointer, size, parameter)      */
+  VI_E_NOMEM = -2,        /* a device or host allocation failed                */
+  VI_E_HIP = -3,          /* a HIP runtime call failed                          */
+  VI_E_STATE = -4,        /* call out of order (e.g. reconstruct before search) */
+  VI_E_EMPTY_SOURCE = -5, /* some level has no hole-free patch (D~ empty)       */
+  VI_E_BUDGET = -6        /* a batch has no room for another context            */
+} vi_status;
+
+typedef enum { VI_RECON_WEIGHTED = 0, VI_RECON_MEAN = 1, VI_RECON_BEST = 2 } vi_recon_mode;
+
+/* Method parameters; vi_params_default() fills the paper's values (Sec. 3.7). */
+typedef struct {
+  int32_t abi_version;  /* 1 */
+  int32_t patch[3];     /* (x, y, t) patch size; only {5, 5, 5} (Sec. 3.7) */
+  int32_t levels;       /* pyramid levels L >= 1 (Sec. 3.6) */
+  int32_t lambda;       /* texture weight in the distance, 50 (Sec. 3.3, 3.7) */
+  int32_t pm_iters;     /* PatchMatch iterations K, 10 (Sec. 3.1, 3.7) */
+  int32_t n_jf;         /* synchronous propagation steps per iteration, 3 */
+  int32_t jf_steps[8];  /* their strides, {4, 2, 1}; each in [1, 4] */
+  double rho;           /* random-search window reduction, 0.5 (Eq. (3.1)) */
+  int32_t em_max_iters; /* at most 20 iterations per level (Alg. 4) */
+  double em_tol;        /* stop when the mean |change| per colour channel per
+                           hole pixel is <= 0.1 (Sec. 3.7); < 0 runs exactly
+                           em_max_iters iterations */
+  int32_t recon_mode;   /* VI_RECON_WEIGHTED (Eqs. (3.2)-(3.3)) or
+                           VI_RECON_MEAN (s = 1); used by every reconstruction
+                           except the final one, which is VI_RECON_BEST */
+  uint64_t seed;        /* key of the Philox4x64-10 random numbers */
+} vi_params;
+
+typedef struct vi_ctx vi_ctx; /* one clip: all its device state */
+
+vi_status vi_params_default(vi_params* out /*(host)*/);
+
+/* Creates a context for one clip and builds, on the GPU, the image and
+ * occlusion pyramids (Alg. 4), the texture features and their pyramid
+ * (Sec. 3.3, Eqs. (3.5), (3.7)) and the source set D~ and target set H~ of
+ * every level (Sec. 2).
+ *   video_rgb (dev) [T][H][W][3] uint8; values where mask = 1 are never read.
+ *   mask      (dev) [T][H][W] uint8; nonzero = occluded (in H).
+ *   hip_stream: hipStream_t used for all work of this context, or NULL for
+ *   the default stream.
+ * The inputs are copied; they may be released once the stream has passed
+ * this call.  Syncs (set sizes are read back).
+ * Errors: VI_E_INVAL (null pointer, unsupported parameter, volume too small
+ * for the levels), VI_E_EMPTY_SOURCE, VI_E_NOMEM, VI_E_HIP. */
+vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, int32_t T,
+                    const uint8_t* video_rgb, const uint8_t* mask, void* hip_stream);
+
+/* dims (host) = (W_l, H_l, T); counts (host) = (|H^l|, |H~^l|, |D~^l|). */
+vi_status vi_level_info(const vi_ctx* ctx, int32_t level, int32_t dims[3], int64_t counts[3]);
+
+/* Byte masks over the level volume (dev, [T][H_l][W_l] each, NULL skips):
+ * hole H^l, sources D~^l, targets H~^l. */
+vi_status vi_level_sets(const vi_ctx* ctx, int32_t level, uint8_t* hole, uint8_t* dsrc,
+                        uint8_t* htil);
+
+/* ANN search of the shift map on H~^level (Sec. 3.1, Alg. 1, Eq. (3.1)),
+ * redesigned as synchronous propagation: targets without a valid match get a
+ * uniform random source of D~; then K iterations of n_jf Jacobi propagation
+ * passes (six axial neighbours at stride s) and one random-search draw per
+ * target.  em_iter keys the random numbers (Philox counter word 1). */
+vi_status vi_nnf_search(vi_ctx* ctx, int32_t level, int32_t em_iter);
+
+/* Reconstruction of H^level (Sec. 3.2): mode VI_RECON_WEIGHTED (Eqs.
+ * (3.2)-(3.3), sigma = nearest-rank 75th percentile), VI_RECON_MEAN or
+ * VI_RECON_BEST (Eq. (3.4)).  Colour and texture are both rebuilt (Eq. (3.8)).
+ *   out_f   (dev) [|H^l|][5] float in [0,1], hole voxels in ascending linear
+ *           order, or NULL.
+ *   absdiff (dev) one uint64 receiving sum over H^l of |new - old| over the
+ *           three colour channels (the stopping test of Alg. 4), or NULL.
+ * Errors: VI_E_STATE if the level has no complete shift map. */
+vi_status vi_reconstruct(vi_ctx* ctx, int32_t level, int32_t mode, float* out_f,
+                         uint64_t* absdiff);
+
+/* The EM loop of one level (Alg. 4 inner loop).  em_iters_run (host) or
+ * NULL.  Syncs once per iteration to read the stopping test, unless em_tol
+ * < 0. */
+vi_status vi_inpaint_level(vi_ctx* ctx, int32_t level, int32_t* em_iters_run);
+
+/* Onion-peel initialisation of the coarsest level (Sec. 3.5, Alg. 3, Eqs.
+ * (3.9)-(3.10)).  layers_run (host) or NULL.  Syncs once per layer. */
+vi_status vi_onion_init(vi_ctx* ctx, int32_t* layers_run);
+
+/* Level transition level+1 -> level (Sec. 3.6): nearest-neighbour upsampling
+ * of the shift map and reconstruction of H^level with recon_mode. */
+vi_status vi_transition(vi_ctx* ctx, int32_t level);
+
+/* The complete algorithm (Alg. 4 without realignment): onion peel, EM loop
+ * per level with transitions, final best-patch reconstruction.
+ *   out_rgb (dev) [T][H][W][3]; voxels outside H equal the input.  Syncs. */
+vi_status vi_inpaint(vi_ctx* ctx, uint8_t* out_rgb);
+
+/* State of a level, for checkpointing and teacher-forced testing (dev
+ * pointers, NULL skips):
+ *   rgbt [T][H_l][W_l][5] uint8;  cand [..] int32 absolute linear index of
+ *   the match, -1 outside H~ or unset;  dist [..] int32 integer SSD, -1
+ *   outside H~;  nvox [..] uint8 number of compared voxels, 0 outside H~.
+ * vi_set_state writes only hole voxels of rgbt and only H~ entries of the
+ * map; it syncs to validate cand (VI_E_INVAL if some cand is outside
+ * [-1, V)).  A map with every H~ entry in D~ counts as complete. */
+vi_status vi_get_state(const vi_ctx* ctx, int32_t level, uint8_t* rgbt, int32_t* cand,
+                       int32_t* dist, uint8_t* nvox);
+vi_status vi_set_state(vi_ctx* ctx, int32_t level, const uint8_t* rgbt, const int32_t* cand,
+                       const int32_t* dist, const uint8_t* nvox);
+
+/* Upper bound of the device bytes vi_create would hold for such a clip
+ * (admission control).  Returns 0 for invalid arguments. */
+size_t vi_footprint_bytes(const vi_params* prm, int32_t W, int32_t H, int32_t T,
+                          double hole_fraction);
+
+/* Device bytes this context holds. */
+size_t vi_ctx_bytes(const vi_ctx* ctx);
+
+/* Rebinds the context to another stream (hipStream_t or NULL). */
+vi_status vi_set_stream(vi_ctx* ctx, void* hip_stream);
+
+/* Frees everything the context owns; NULL-safe.  Syncs its stream. */
+void vi_destroy(vi_ctx* ctx);
+
+/* Thread-local message of the last error (never NULL). */
+const char* vi_last_error(void);
+
+/* Nominal patch-distance evaluations of one vi_nnf_search at a level:
+ * |H~^l| * (1 + sum over iterations k of (6 n_jf + [floor(r_max rho^k) >= 1]))
+ * (the initial evaluation, six neighbour candidates per propagation pass,
+ * one random candidate per iteration).  Returns -1 on error. */
+int64_t vi_nominal_evals(const vi_ctx* ctx, int32_t level);
+
+/* Work counters of a context since creation or the last reset (host out).
+ * effective_evals is read back from the device: syncs. */
+typedef struct {
+  int64_t nominal_evals;   /* sum of the nominal counts of every search run */
+  int64_t effective_evals; /* distances actually computed */
+  int64_t searches;        /* searches run (EM iterations and onion layers) */
+  int64_t em_iters;        /* EM iterations run (all levels) */
+  int64_t recon_pixels;    /* hole pixels reconstructed (all reconstructions) */
+} vi_counters;
+vi_status vi_get_counters(vi_ctx* ctx, vi_counters* out);
+vi_status vi_reset_counters(vi_ctx* ctx);
+
+/* Kernel timing with HIP events recorded on the context's stream around
+ * every launch of the hot path while profiling is on. */
+typedef enum {
+  VI_K_INIT = 0,   /* search step 0; units = targets */
+  VI_K_PASS = 1,   /* propagation / random-search pass; units = nominal evals */
+  VI_K_RECON = 2,  /* reconstruction; units = hole pixels */
+  VI_K_OTHER = 3,  /* upsampling, copies; units = voxels */
+  VI_K_ONION = 4   /* any launch of the onion-peel initialisation */
+} vi_kernel_kind;
+typedef struct {
+  int32_t kind;  /* vi_kernel_kind */
+  int32_t level;
+  int64_t units;
+  float ms;
+} vi_kernel_time;
+vi_status vi_profile(vi_ctx* ctx, int32_t on);
+/* Copies up to cap records (host) of the launches timed since the last read
+ * and clears them; returns the number of records or a negative status.
+ * Syncs. */
+int32_t vi_profile_read(vi_ctx* ctx, vi_kernel_time* out, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -139,6 +139,7 @@ void vio_destroy(vio_ctx* ctx) {
 static int build_sets(vio_ctx* ctx, level_t* L) {
   const int hx = ctx->prm.patch[0] / 2, hy = ctx->prm.patch[1] / 2, ht = ctx->prm.patch[2] / 2;
   int64_t nD = 0, nH = 0, nHt = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nD, nH, nHt)
   for (int32_t t = 0; t < L->T; ++t)
     for (int32_t y = 0; y < L->H; ++y)
       for (int32_t x = 0; x < L->W; ++x) {
@@ -282,6 +283,7 @@ int vio_create(vio_ctx** out, const vio_params* prm, int32_t W, int32_t H, int32
   for (int l = 1; l < ctx->L; ++l) {
     level_t* F = &ctx->lv[l - 1];
     level_t* C = &ctx->lv[l];
+#pragma omp parallel for schedule(static)
     for (int32_t t = 0; t < C->T; ++t)
       for (int32_t y = 0; y < C->H; ++y)
         for (int32_t x = 0; x < C->W; ++x) {
@@ -729,6 +731,8 @@ int vio_inpaint_level(vio_ctx* ctx, int32_t level, int32_t* iters_run) {
       e = (double)s / (3.0 * (double)L->nH);
     } while (e > ctx->prm.em_tol && k < ctx->prm.em_max_iters);
   }
+  /* with no hole the target set is empty and the (empty) map is complete */
+  L->searched = 1;
   if (iters_run) *iters_run = k;
   return VIO_OK;
 }

@@ -1,0 +1,682 @@
+// vi_api.cpp -- host orchestration and C ABI of libvi (see include/vi.h).
+//
+// Every step of the method runs in the kernels of vi_kernels.hip; this file
+// validates arguments, owns device memory, sequences launches on the
+// context's stream and implements the control flow of Alg. 4 (onion peel,
+// EM loop with its stopping test, level transitions, final reconstruction).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "vi.h"
+#include "vi_internal.h"
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+vi_status fail(vi_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define VI_HIP(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(VI_E_HIP, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define VI_TRY(expr)               \
+  do {                             \
+    vi_status s_ = (expr);         \
+    if (s_ != VI_OK) return s_;    \
+  } while (0)
+
+constexpr int kMaxLevels = 8;
+
+struct Level {
+  vi::DevLevel d{};
+  int32_t nH = 0, nS = 0;
+  int32_t* hlist = nullptr;
+  int32_t* tlist = nullptr;
+  bool complete = false;
+};
+
+}  // namespace
+
+struct vi_ctx {
+  vi_params prm{};
+  int32_t L = 0;
+  int32_t W = 0, H = 0, T = 0;
+  hipStream_t st = nullptr;
+  Level lv[kMaxLevels];
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  void* ctemp = nullptr;  // compaction scratch
+  size_t ctemp_bytes = 0;
+  int32_t* d_count = nullptr;             // [2]
+  unsigned long long* d_u64 = nullptr;    // [0] absdiff, [1..2] set_state checks, [3] evals
+  // onion-peel scratch (coarsest level)
+  uint8_t *o_Hp = nullptr, *o_E = nullptr, *o_bd = nullptr, *o_S = nullptr;
+  uint8_t *o_t1 = nullptr, *o_t2 = nullptr;
+  int32_t *o_tl = nullptr, *o_pl = nullptr;
+  // work counters (host side; effective evaluations live in d_u64[3])
+  int64_t n_nominal = 0, n_searches = 0, n_em = 0, n_recon = 0;
+  // kernel timing with events on the context's stream
+  bool profiling = false;
+  int32_t kind_override = -1;  // every launch of the onion peel is VI_K_ONION
+  struct Rec {
+    int32_t kind, level;
+    int64_t units;
+    int ev;
+  };
+  std::vector<hipEvent_t> events;  // pairs (start, stop)
+  std::vector<Rec> recs;
+};
+
+namespace {
+
+template <typename T>
+vi_status dalloc(vi_ctx* c, T** p, size_t n) {
+  void* q = nullptr;
+  const size_t b = n * sizeof(T) > 0 ? n * sizeof(T) : 16;
+  if (hipMalloc(&q, b) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(VI_E_NOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+  }
+  c->allocs.push_back(q);
+  c->bytes += b;
+  *p = static_cast<T*>(q);
+  return VI_OK;
+}
+
+void dfree(vi_ctx* c, void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < c->allocs.size(); ++i)
+    if (c->allocs[i] == p) {
+      size_t sz = 0;
+      (void)hipMemPtrGetInfo(p, &sz);
+      c->bytes -= sz;
+      (void)hipFree(p);
+      c->allocs.erase(c->allocs.begin() + (long)i);
+      return;
+    }
+}
+
+vi_status launched(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return fail(VI_E_HIP, std::string("launch of ") + what + " failed: " + hipGetErrorString(e));
+  return VI_OK;
+}
+
+// event pair around a launch while profiling; returns the record index or -1
+int prof_begin(vi_ctx* c) {
+  if (!c->profiling) return -1;
+  const size_t need = 2 * (c->recs.size() + 1);
+  while (c->events.size() < need) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      return -1;
+    }
+    c->events.push_back(e);
+  }
+  const int ev = (int)(2 * c->recs.size());
+  if (hipEventRecord(c->events[ev], c->st) != hipSuccess) return -1;
+  c->recs.push_back({0, 0, 0, ev});
+  return (int)c->recs.size() - 1;
+}
+
+void prof_end(vi_ctx* c, int r, int32_t kind, int32_t level, int64_t units) {
+  if (r < 0) return;
+  vi_ctx::Rec& rec = c->recs[(size_t)r];
+  rec.kind = c->kind_override >= 0 ? c->kind_override : kind;
+  rec.level = level;
+  rec.units = units;
+  (void)hipEventRecord(c->events[(size_t)rec.ev + 1], c->st);
+}
+
+int64_t per_target_evals(const vi_params& p, int32_t rmax);
+
+vi_status check_params(const vi_params* p) {
+  if (!p) return fail(VI_E_INVAL, "null params");
+  if (p->abi_version != 1) return fail(VI_E_INVAL, "abi_version must be 1");
+  if (p->patch[0] != 5 || p->patch[1] != 5 || p->patch[2] != 5)
+    return fail(VI_E_INVAL, "only 5x5x5 patches are supported");
+  if (p->levels < 1 || p->levels > kMaxLevels) return fail(VI_E_INVAL, "levels must be in [1, 8]");
+  if (p->lambda < 0 || p->lambda > 130) return fail(VI_E_INVAL, "lambda must be in [0, 130]");
+  if (p->pm_iters < 0 || p->pm_iters > 64) return fail(VI_E_INVAL, "pm_iters must be in [0, 64]");
+  if (p->n_jf < 0 || p->n_jf > 8) return fail(VI_E_INVAL, "n_jf must be in [0, 8]");
+  for (int i = 0; i < p->n_jf; ++i)
+    if (p->jf_steps[i] < 1 || p->jf_steps[i] > 4)
+      return fail(VI_E_INVAL, "jump-flood steps must be in [1, 4]");
+  if (!(p->rho > 0.0 && p->rho <= 1.0)) return fail(VI_E_INVAL, "rho must be in (0, 1]");
+  if (p->em_max_iters < 1) return fail(VI_E_INVAL, "em_max_iters must be >= 1");
+  if (p->recon_mode != VI_RECON_WEIGHTED && p->recon_mode != VI_RECON_MEAN)
+    return fail(VI_E_INVAL, "recon_mode must be WEIGHTED or MEAN");
+  return VI_OK;
+}
+
+vi_status check_dims(const vi_params* p, int32_t W, int32_t H, int32_t T) {
+  if (W < 5 || H < 5 || T < 5 || W >= 32768 || H >= 32768 || T >= 32768)
+    return fail(VI_E_INVAL, "W, H, T must be in [5, 32768)");
+  if ((int64_t)W * H * T >= (int64_t(1) << 31)) return fail(VI_E_INVAL, "W*H*T must be < 2^31");
+  int32_t w = W, h = H;
+  for (int l = 1; l < p->levels; ++l) {
+    w = (w + 1) / 2;
+    h = (h + 1) / 2;
+  }
+  if (w < 5 || h < 5) return fail(VI_E_INVAL, "the coarsest level is smaller than a patch");
+  return VI_OK;
+}
+
+vi_status sync(vi_ctx* c) {
+  VI_HIP(hipStreamSynchronize(c->st));
+  return VI_OK;
+}
+
+// stable compaction of flags into a fresh exact-size list
+vi_status compact_to(vi_ctx* c, const uint8_t* flags, int32_t n, int32_t* scratch,
+                     int32_t** out, int32_t* count) {
+  VI_HIP(vi::compact(c->st, flags, n, scratch, c->d_count, c->ctemp, c->ctemp_bytes));
+  int32_t h = 0;
+  VI_HIP(hipMemcpyAsync(&h, c->d_count, sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+  VI_TRY(sync(c));
+  VI_TRY(dalloc(c, out, (size_t)h));
+  if (h > 0)
+    VI_HIP(hipMemcpyAsync(*out, scratch, sizeof(int32_t) * (size_t)h, hipMemcpyDeviceToDevice,
+                          c->st));
+  *count = h;
+  return VI_OK;
+}
+
+int32_t r_max(const vi::DevLevel& d) {
+  int32_t r = d.W > d.H ? d.W : d.H;
+  return r > d.T ? r : d.T;
+}
+
+int32_t rs_radius(const vi_params& p, int32_t rmax, int k) {
+  double r = (double)rmax;
+  for (int i = 0; i < k; ++i) r *= p.rho;
+  return (int32_t)std::floor(r);
+}
+
+// nominal evaluations per target of one search: the initial evaluation, six
+// neighbour candidates per propagation pass, one random candidate per
+// iteration with a radius of at least one
+int64_t per_target_evals(const vi_params& p, int32_t rmax) {
+  int64_t per = 1;
+  for (int k = 1; k <= p.pm_iters; ++k)
+    per += 6 * p.n_jf + (rs_radius(p, rmax, k) >= 1 ? 1 : 0);
+  return per;
+}
+
+// ANN search over a target list (Sec. 3.1, Alg. 1): step 0, then K
+// iterations of propagation passes with the random search fused into the
+// last pass.  The result always ends in nnf0.
+vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
+                 const uint8_t* smask, const uint8_t* excl, uint64_t step) {
+  Level& lv = c->lv[level];
+  const vi::DevLevel& d = lv.d;
+  if (nS <= 0) return VI_OK;
+  const int32_t rmax = r_max(d);
+  c->n_nominal += per_target_evals(c->prm, rmax) * (int64_t)nS;
+  c->n_searches += 1;
+  vi::PassArgs A{};
+  A.tlist = tlist;
+  A.nS = nS;
+  A.smask = smask;
+  A.excl = excl;
+  A.step = step;
+  A.evals = c->d_u64 + 3;
+  A.nin = d.nnf0;
+  A.nout = d.nnf0;
+  int r = prof_begin(c);
+  vi::launch_s0(c->st, d, A);
+  prof_end(c, r, VI_K_INIT, level, nS);
+  VI_TRY(launched("s0"));
+  int2* buf[2] = {d.nnf0, d.nnf1};
+  int cur = 0;
+  for (int k = 1; k <= c->prm.pm_iters; ++k) {
+    const int32_t R = rs_radius(c->prm, rmax, k);
+    const bool rs = R >= 1;
+    const int np = c->prm.n_jf > 0 ? c->prm.n_jf : 1;
+    if (c->prm.n_jf == 0 && !rs) continue;
+    for (int js = 0; js < np; ++js) {
+      A.nin = buf[cur];
+      A.nout = buf[cur ^ 1];
+      A.s = c->prm.n_jf > 0 ? c->prm.jf_steps[js] : 0;
+      A.rs_k = (js == np - 1 && rs) ? k : 0;
+      A.R = R;
+      r = prof_begin(c);
+      vi::launch_pass(c->st, d, A);
+      prof_end(c, r, VI_K_PASS, level,
+               (int64_t)nS * ((A.s > 0 ? 6 : 0) + (A.rs_k > 0 ? 1 : 0)));
+      VI_TRY(launched("pass"));
+      cur ^= 1;
+    }
+  }
+  if (cur == 1) {
+    r = prof_begin(c);
+    vi::launch_copy_targets(c->st, tlist, nS, d.nnf1, d.nnf0);
+    prof_end(c, r, VI_K_OTHER, level, nS);
+    VI_TRY(launched("copy"));
+  }
+  return VI_OK;
+}
+
+vi_status recon(vi_ctx* c, int32_t level, const int32_t* plist, int32_t nP, const uint8_t* excl,
+                int mode, float* out_f, unsigned long long* absdiff) {
+  if (absdiff) vi::launch_fill_u64(c->st, absdiff, 1);
+  c->n_recon += nP;
+  const int r = prof_begin(c);
+  vi::launch_recon(c->st, c->lv[level].d, plist, nP, excl, mode, out_f, absdiff);
+  prof_end(c, r, VI_K_RECON, level, nP);
+  return launched("recon");
+}
+
+vi_status level_ok(const vi_ctx* c, int32_t level) {
+  if (!c) return fail(VI_E_INVAL, "null context");
+  if (level < 0 || level >= c->L) return fail(VI_E_INVAL, "level out of range");
+  return VI_OK;
+}
+
+vi_status inpaint_level(vi_ctx* c, int32_t level, int32_t* iters) {
+  Level& lv = c->lv[level];
+  int32_t k = 0;
+  if (lv.nH > 0) {
+    double e;
+    do {
+      VI_TRY(search(c, level, lv.tlist, lv.nS, lv.d.htil, nullptr, (uint64_t)k));
+      VI_TRY(recon(c, level, lv.hlist, lv.nH, nullptr, c->prm.recon_mode, nullptr, c->d_u64));
+      ++k;
+      ++c->n_em;
+      if (c->prm.em_tol < 0) {
+        e = INFINITY;
+      } else {
+        unsigned long long s = 0;
+        VI_HIP(hipMemcpyAsync(&s, c->d_u64, sizeof(s), hipMemcpyDeviceToHost, c->st));
+        VI_TRY(sync(c));
+        e = (double)s / (3.0 * (double)lv.nH);
+      }
+    } while (e > c->prm.em_tol && k < c->prm.em_max_iters);
+  }
+  lv.complete = true;
+  if (iters) *iters = k;
+  return VI_OK;
+}
+
+vi_status onion(vi_ctx* c, int32_t* layers_run) {
+  const int32_t level = c->L - 1;
+  Level& lv = c->lv[level];
+  const vi::DevLevel& d = lv.d;
+  const size_t V = (size_t)d.V;
+  if (!c->o_Hp) {
+    VI_TRY(dalloc(c, &c->o_Hp, V));
+    VI_TRY(dalloc(c, &c->o_E, V));
+    VI_TRY(dalloc(c, &c->o_bd, V));
+    VI_TRY(dalloc(c, &c->o_S, V));
+    VI_TRY(dalloc(c, &c->o_t1, V));
+    VI_TRY(dalloc(c, &c->o_t2, V));
+    VI_TRY(dalloc(c, &c->o_tl, V));
+    VI_TRY(dalloc(c, &c->o_pl, V));
+  }
+  vi::launch_fill_nnf(c->st, d.nnf0, d.nvox, d.V);
+  vi::launch_fill_nnf(c->st, d.nnf1, nullptr, d.V);
+  VI_HIP(hipMemcpyAsync(c->o_Hp, d.hole, V, hipMemcpyDeviceToDevice, c->st));
+  uint8_t* Hp = c->o_Hp;
+  uint8_t* E = c->o_E;
+  int32_t layer = 0;
+  struct Kind {
+    vi_ctx* c;
+    ~Kind() { c->kind_override = -1; }
+  } kind_guard{c};
+  c->kind_override = VI_K_ONION;
+  for (;;) {
+    const int r = prof_begin(c);
+    vi::launch_erode3(c->st, Hp, E, c->o_bd, d.W, d.H, d.T);
+    vi::launch_dilate5(c->st, c->o_bd, c->o_S, c->o_t1, c->o_t2, d.W, d.H, d.T, Hp);
+    prof_end(c, r, VI_K_OTHER, level, d.V);
+    VI_TRY(launched("onion layer"));
+    VI_HIP(vi::compact(c->st, c->o_bd, d.V, c->o_pl, c->d_count, c->ctemp, c->ctemp_bytes));
+    VI_HIP(vi::compact(c->st, c->o_S, d.V, c->o_tl, c->d_count + 1, c->ctemp, c->ctemp_bytes));
+    int32_t cnt[2] = {0, 0};
+    VI_HIP(hipMemcpyAsync(cnt, c->d_count, sizeof(cnt), hipMemcpyDeviceToHost, c->st));
+    VI_TRY(sync(c));
+    if (cnt[0] == 0) break;  // no layer left: H' is empty
+    VI_TRY(search(c, level, c->o_tl, cnt[1], c->o_S, Hp, (uint64_t(1) << 32) + (uint64_t)layer));
+    VI_TRY(recon(c, level, c->o_pl, cnt[0], Hp, c->prm.recon_mode, nullptr, nullptr));
+    uint8_t* t = Hp;
+    Hp = E;
+    E = t;
+    ++layer;
+  }
+  lv.complete = false;  // the innermost layer's targets may be unmatched
+  if (layers_run) *layers_run = layer;
+  return VI_OK;
+}
+
+vi_status transition(vi_ctx* c, int32_t level) {
+  Level& F = c->lv[level];
+  Level& C = c->lv[level + 1];
+  if (!C.complete) return fail(VI_E_STATE, "the coarser level has no complete shift map");
+  const int r = prof_begin(c);
+  vi::launch_upsample(c->st, F.d, C.d, F.tlist, F.nS);
+  prof_end(c, r, VI_K_OTHER, level, F.nS);
+  VI_TRY(launched("upsample"));
+  F.complete = true;
+  return recon(c, level, F.hlist, F.nH, nullptr, c->prm.recon_mode, nullptr, nullptr);
+}
+
+}  // namespace
+
+extern "C" {
+
+vi_status vi_params_default(vi_params* o) {
+  if (!o) return fail(VI_E_INVAL, "null params");
+  std::memset(o, 0, sizeof(*o));
+  o->abi_version = 1;
+  o->patch[0] = o->patch[1] = o->patch[2] = 5;
+  o->levels = 1;
+  o->lambda = 50;
+  o->pm_iters = 10;
+  o->n_jf = 3;
+  o->jf_steps[0] = 4;
+  o->jf_steps[1] = 2;
+  o->jf_steps[2] = 1;
+  o->rho = 0.5;
+  o->em_max_iters = 20;
+  o->em_tol = 0.1;
+  o->recon_mode = VI_RECON_WEIGHTED;
+  o->seed = 0;
+  return VI_OK;
+}
+
+const char* vi_last_error(void) { return g_err.c_str(); }
+
+size_t vi_footprint_bytes(const vi_params* prm, int32_t W, int32_t H, int32_t T,
+                          double hole_fraction) {
+  if (check_params(prm) != VI_OK || check_dims(prm, W, H, T) != VI_OK) return 0;
+  if (!(hole_fraction >= 0.0 && hole_fraction <= 1.0)) return 0;
+  size_t total = 0;
+  int64_t w = W, h = H;
+  const int64_t V0 = (int64_t)W * H * T;
+  for (int l = 0; l < prm->levels; ++l) {
+    const int64_t V = w * h * T;
+    // vox 8, hole/dsrc/htil 3, nnf 16, nvox 1, source list 4
+    total += (size_t)V * 32;
+    // target and hole lists: the dilated hole is at most 125x the hole
+    const double fr = hole_fraction * 125.0 < 1.0 ? hole_fraction * 125.0 : 1.0;
+    total += (size_t)((double)V * (fr + hole_fraction) * 4.0) + 4096;
+    w = (w + 1) / 2;
+    h = (h + 1) / 2;
+  }
+  // creation temporaries at the finest level: gradients 4, box sums 8,
+  // dilation scratch 2, compaction list 4
+  total += (size_t)V0 * 18;
+  return total + (size_t)(64u << 20);
+}
+
+vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, int32_t T,
+                    const uint8_t* video_rgb, const uint8_t* mask, void* hip_stream) {
+  if (!out) return fail(VI_E_INVAL, "null output handle");
+  *out = nullptr;
+  VI_TRY(check_params(prm));
+  VI_TRY(check_dims(prm, W, H, T));
+  if (!video_rgb || !mask) return fail(VI_E_INVAL, "null input pointer");
+  vi_ctx* c = new (std::nothrow) vi_ctx();
+  if (!c) return fail(VI_E_NOMEM, "host allocation failed");
+  c->prm = *prm;
+  c->L = prm->levels;
+  c->W = W;
+  c->H = H;
+  c->T = T;
+  c->st = static_cast<hipStream_t>(hip_stream);
+  vi_status st = VI_OK;
+  auto bail = [&](vi_status s) {
+    vi_destroy(c);
+    return s;
+  };
+  // level geometry and buffers
+  int32_t w = W, h = H;
+  for (int l = 0; l < c->L; ++l) {
+    vi::DevLevel& d = c->lv[l].d;
+    d.W = w;
+    d.H = h;
+    d.T = T;
+    d.WH = w * h;
+    d.V = w * h * T;
+    d.level = l;
+    d.fdW = vi::make_fastdiv((uint32_t)w);
+    d.fdWH = vi::make_fastdiv((uint32_t)(w * h));
+    d.lambda = prm->lambda;
+    d.seed = prm->seed;
+    const size_t V = (size_t)d.V;
+    if ((st = dalloc(c, &d.vox, V)) || (st = dalloc(c, &d.hole, V)) ||
+        (st = dalloc(c, &d.dsrc, V)) || (st = dalloc(c, &d.htil, V)) ||
+        (st = dalloc(c, &d.nnf0, V)) ||
+        (st = dalloc(c, &d.nnf1, V)) || (st = dalloc(c, &d.nvox, V)))
+      return bail(st);
+    w = (w + 1) / 2;
+    h = (h + 1) / 2;
+  }
+  const vi::DevLevel& L0 = c->lv[0].d;
+  const size_t V0 = (size_t)L0.V;
+  if ((st = dalloc(c, &c->d_count, 4)) || (st = dalloc(c, &c->d_u64, 8))) return bail(st);
+  vi::launch_fill_u64(c->st, c->d_u64, 8);
+  c->ctemp_bytes = vi::compact_temp_bytes(L0.V);
+  if ((st = dalloc(c, reinterpret_cast<uint8_t**>(&c->ctemp), c->ctemp_bytes))) return bail(st);
+  // creation temporaries
+  uint32_t* gpk = nullptr;
+  uint2* hsum = nullptr;
+  uint8_t *t1 = nullptr, *t2 = nullptr;
+  int32_t* scratch = nullptr;
+  if ((st = dalloc(c, &gpk, V0)) || (st = dalloc(c, &hsum, V0)) || (st = dalloc(c, &t1, V0)) ||
+      (st = dalloc(c, &t2, V0)) || (st = dalloc(c, &scratch, V0)))
+    return bail(st);
+  // pyramids (Alg. 4) and texture features (Sec. 3.3)
+  vi::launch_init_level0(c->st, video_rgb, mask, L0);
+  for (int l = 1; l < c->L; ++l) vi::launch_pyr_down(c->st, c->lv[l - 1].d, c->lv[l].d);
+  const int32_t s = 1 << (c->L - 1);
+  vi::launch_texture(c->st, video_rgb, L0, s, gpk, hsum);
+  for (int l = 0; l < c->L; ++l) vi::launch_texture_level(c->st, hsum, L0, c->lv[l].d, l, s);
+  if ((st = launched("pyramids"))) return bail(st);
+  // sets (Sec. 2), empty shift maps
+  for (int l = 0; l < c->L; ++l) {
+    Level& lv = c->lv[l];
+    vi::DevLevel& d = lv.d;
+    vi::launch_dilate5(c->st, d.hole, d.htil, t1, t2, d.W, d.H, d.T, nullptr);
+    vi::launch_sources(c->st, d);
+    vi::launch_fill_nnf(c->st, d.nnf0, d.nvox, d.V);
+    vi::launch_fill_nnf(c->st, d.nnf1, nullptr, d.V);
+    if ((st = launched("sets"))) return bail(st);
+    if ((st = compact_to(c, d.dsrc, d.V, scratch, &d.dlist, &d.nD))) return bail(st);
+    if ((st = compact_to(c, d.htil, d.V, scratch, &lv.tlist, &lv.nS))) return bail(st);
+    if ((st = compact_to(c, d.hole, d.V, scratch, &lv.hlist, &lv.nH))) return bail(st);
+    if (d.nD == 0) return bail(fail(VI_E_EMPTY_SOURCE, "level " + std::to_string(l) +
+                                                           " has no hole-free patch"));
+  }
+  if ((st = sync(c))) return bail(st);
+  dfree(c, gpk);
+  dfree(c, hsum);
+  dfree(c, t1);
+  dfree(c, t2);
+  dfree(c, scratch);
+  *out = c;
+  return VI_OK;
+}
+
+void vi_destroy(vi_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->st);
+  for (void* p : c->allocs) (void)hipFree(p);
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  delete c;
+}
+
+vi_status vi_set_stream(vi_ctx* c, void* hip_stream) {
+  if (!c) return fail(VI_E_INVAL, "null context");
+  c->st = static_cast<hipStream_t>(hip_stream);
+  return VI_OK;
+}
+
+size_t vi_ctx_bytes(const vi_ctx* c) { return c ? c->bytes : 0; }
+
+vi_status vi_level_info(const vi_ctx* c, int32_t level, int32_t dims[3], int64_t counts[3]) {
+  VI_TRY(level_ok(c, level));
+  const Level& lv = c->lv[level];
+  if (dims) {
+    dims[0] = lv.d.W;
+    dims[1] = lv.d.H;
+    dims[2] = lv.d.T;
+  }
+  if (counts) {
+    counts[0] = lv.nH;
+    counts[1] = lv.nS;
+    counts[2] = lv.d.nD;
+  }
+  return VI_OK;
+}
+
+vi_status vi_level_sets(const vi_ctx* c, int32_t level, uint8_t* hole, uint8_t* dsrc,
+                        uint8_t* htil) {
+  VI_TRY(level_ok(c, level));
+  const vi::DevLevel& d = c->lv[level].d;
+  const size_t V = (size_t)d.V;
+  if (hole) VI_HIP(hipMemcpyAsync(hole, d.hole, V, hipMemcpyDeviceToDevice, c->st));
+  if (dsrc) VI_HIP(hipMemcpyAsync(dsrc, d.dsrc, V, hipMemcpyDeviceToDevice, c->st));
+  if (htil) VI_HIP(hipMemcpyAsync(htil, d.htil, V, hipMemcpyDeviceToDevice, c->st));
+  return VI_OK;
+}
+
+vi_status vi_nnf_search(vi_ctx* c, int32_t level, int32_t em_iter) {
+  VI_TRY(level_ok(c, level));
+  if (em_iter < 0) return fail(VI_E_INVAL, "em_iter must be >= 0");
+  Level& lv = c->lv[level];
+  VI_TRY(search(c, level, lv.tlist, lv.nS, lv.d.htil, nullptr, (uint64_t)em_iter));
+  lv.complete = true;
+  return VI_OK;
+}
+
+vi_status vi_reconstruct(vi_ctx* c, int32_t level, int32_t mode, float* out_f,
+                         uint64_t* absdiff) {
+  VI_TRY(level_ok(c, level));
+  if (mode != VI_RECON_WEIGHTED && mode != VI_RECON_MEAN && mode != VI_RECON_BEST)
+    return fail(VI_E_INVAL, "bad reconstruction mode");
+  Level& lv = c->lv[level];
+  if (!lv.complete) return fail(VI_E_STATE, "no complete shift map at this level");
+  return recon(c, level, lv.hlist, lv.nH, nullptr, mode, out_f,
+               reinterpret_cast<unsigned long long*>(absdiff));
+}
+
+vi_status vi_inpaint_level(vi_ctx* c, int32_t level, int32_t* em_iters_run) {
+  VI_TRY(level_ok(c, level));
+  return inpaint_level(c, level, em_iters_run);
+}
+
+vi_status vi_onion_init(vi_ctx* c, int32_t* layers_run) {
+  if (!c) return fail(VI_E_INVAL, "null context");
+  return onion(c, layers_run);
+}
+
+vi_status vi_transition(vi_ctx* c, int32_t level) {
+  VI_TRY(level_ok(c, level));
+  if (level + 1 >= c->L) return fail(VI_E_INVAL, "no coarser level");
+  return transition(c, level);
+}
+
+vi_status vi_inpaint(vi_ctx* c, uint8_t* out_rgb) {
+  if (!c || !out_rgb) return fail(VI_E_INVAL, "null argument");
+  VI_TRY(onion(c, nullptr));
+  for (int32_t l = c->L - 1; l >= 0; --l) {
+    if (l < c->L - 1) VI_TRY(transition(c, l));
+    VI_TRY(inpaint_level(c, l, nullptr));
+  }
+  Level& l0 = c->lv[0];
+  if (l0.nH > 0) VI_TRY(recon(c, 0, l0.hlist, l0.nH, nullptr, VI_RECON_BEST, nullptr, nullptr));
+  vi::launch_out_rgb(c->st, l0.d, out_rgb);
+  VI_TRY(launched("output"));
+  return sync(c);
+}
+
+vi_status vi_get_state(const vi_ctx* c, int32_t level, uint8_t* rgbt, int32_t* cand,
+                       int32_t* dist, uint8_t* nvox) {
+  VI_TRY(level_ok(c, level));
+  vi::launch_get_state(c->st, c->lv[level].d, rgbt, cand, dist, nvox);
+  return launched("get_state");
+}
+
+vi_status vi_set_state(vi_ctx* c, int32_t level, const uint8_t* rgbt, const int32_t* cand,
+                       const int32_t* dist, const uint8_t* nvox) {
+  VI_TRY(level_ok(c, level));
+  vi::launch_fill_u64(c->st, c->d_u64 + 1, 2);
+  vi::launch_set_state(c->st, c->lv[level].d, rgbt, cand, dist, nvox, c->d_u64 + 1);
+  VI_TRY(launched("set_state"));
+  unsigned long long bad[2] = {0, 0};
+  VI_HIP(hipMemcpyAsync(bad, c->d_u64 + 1, sizeof(bad), hipMemcpyDeviceToHost, c->st));
+  VI_TRY(sync(c));
+  if (bad[0]) return fail(VI_E_INVAL, "cand outside [-1, V)");
+  if (cand) c->lv[level].complete = bad[1] == 0;
+  return VI_OK;
+}
+
+int64_t vi_nominal_evals(const vi_ctx* c, int32_t level) {
+  if (level_ok(c, level) != VI_OK) return -1;
+  const Level& lv = c->lv[level];
+  return per_target_evals(c->prm, r_max(lv.d)) * (int64_t)lv.nS;
+}
+
+vi_status vi_get_counters(vi_ctx* c, vi_counters* out) {
+  if (!c || !out) return fail(VI_E_INVAL, "null argument");
+  unsigned long long v = 0;
+  VI_HIP(hipMemcpyAsync(&v, c->d_u64 + 3, sizeof(v), hipMemcpyDeviceToHost, c->st));
+  VI_TRY(sync(c));
+  out->nominal_evals = c->n_nominal;
+  out->effective_evals = (int64_t)v;
+  out->searches = c->n_searches;
+  out->em_iters = c->n_em;
+  out->recon_pixels = c->n_recon;
+  return VI_OK;
+}
+
+vi_status vi_reset_counters(vi_ctx* c) {
+  if (!c) return fail(VI_E_INVAL, "null context");
+  c->n_nominal = c->n_searches = c->n_em = c->n_recon = 0;
+  vi::launch_fill_u64(c->st, c->d_u64 + 3, 1);
+  return launched("fill");
+}
+
+vi_status vi_profile(vi_ctx* c, int32_t on) {
+  if (!c) return fail(VI_E_INVAL, "null context");
+  c->profiling = on != 0;
+  return VI_OK;
+}
+
+int32_t vi_profile_read(vi_ctx* c, vi_kernel_time* out, int32_t cap) {
+  if (!c || (cap > 0 && !out) || cap < 0) return fail(VI_E_INVAL, "bad argument");
+  if (sync(c) != VI_OK) return VI_E_HIP;
+  const int32_t n = (int32_t)c->recs.size() < cap ? (int32_t)c->recs.size() : cap;
+  for (int32_t i = 0; i < n; ++i) {
+    const vi_ctx::Rec& r = c->recs[(size_t)i];
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->events[(size_t)r.ev], c->events[(size_t)r.ev + 1]) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      ms = -1.f;
+    }
+    out[i].kind = r.kind;
+    out[i].level = r.level;
+    out[i].units = r.units;
+    out[i].ms = ms;
+  }
+  c->recs.clear();
+  return n;
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// vi_internal.h -- device-side data layout and kernel launchers of libvi.
+//
+// Per pyramid level the context keeps, in HBM:
+//   vox    uint2 [V]  .x = R | G<<8 | B<<16, .y = Tx | Ty<<8 (one 8-byte load
+//                     per voxel feeds two v_dot4_u32_u8 operations)
+//   hole   u8 [V]     H^l
+//   dsrc   u8 [V]     D~^l (centres of hole-free, in-volume patches)
+//   htil   u8 [V]     H~^l (targets of the shift map)
+//   dlist  i32 [nD]   D~ in ascending linear order (uniform random init)
+//   tlist  i32 [nS]   H~ in ascending linear order (one thread per target)
+//   hlist  i32 [nH]   H  in ascending linear order (one wave per hole pixel)
+//   nnf0/1 int2 [V]   (cand, dist) double buffer of the Jacobi passes; entries
+//                     outside the current target set are never read
+//   nvox   u8 [V]     number of voxels the stored distance compared
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vi {
+
+// Division by a run-time invariant divisor (Granlund & Montgomery, "Division
+// by invariant integers using multiplication", PLDI 1994): q = (mulhi(m, n) +
+// n) >> l, exact for 0 <= n < 2^31 and 1 <= d < 2^31.
+struct FastDiv {
+  uint32_t d, m, l;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  f.l = l;
+  f.m = (uint32_t)((((1ull << 32) * ((1ull << l) - d)) / d) + 1);
+  return f;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+  return (__umulhi(n, f.m) + n) >> f.l;
+}
+
+struct DevLevel {
+  int32_t W, H, T, V, WH, level;
+  FastDiv fdW, fdWH;
+  uint2* vox;
+  uint8_t* hole;
+  uint8_t* dsrc;
+  uint8_t* htil;
+  int32_t* dlist;
+  int32_t nD;
+  int2* nnf0;
+  int2* nnf1;
+  uint8_t* nvox;
+  int32_t lambda;
+  uint64_t seed;
+};
+
+// One synchronous pass of the search over a target list.
+struct PassArgs {
+  const int32_t* tlist;
+  int32_t nS;
+  const uint8_t* smask;    // target-set membership (q in S)
+  const uint8_t* excl;     // voxels excluded from comparisons (onion: H'), or null
+  const int2* nin;         // state before the pass
+  int2* nout;              // state after the pass
+  int32_t s;               // propagation stride, 0 = no propagation
+  int32_t rs_k;            // PatchMatch iteration of the random search, 0 = none
+  int32_t R;               // random-search radius floor(r_max rho^k)
+  uint64_t step;           // Philox counter word 1
+  unsigned long long* evals;  // effective-evaluation counter, or null
+};
+
+// ---------------------------------------------------------------- launchers
+// All launch on `st`; none synchronises.
+void launch_init_level0(hipStream_t st, const uint8_t* rgb, const uint8_t* mask, DevLevel L0);
+void launch_pyr_down(hipStream_t st, DevLevel F, DevLevel C);
+void launch_texture(hipStream_t st, const uint8_t* rgb, DevLevel L0, int32_t s,
+                    uint32_t* gpk, uint2* hsum);
+void launch_texture_level(hipStream_t st, const uint2* hsum, DevLevel L0, DevLevel Ll,
+                          int32_t l, int32_t s);
+// separable 5x5x5 box dilation of src into dst (tmp: two scratch volumes)
+void launch_dilate5(hipStream_t st, const uint8_t* src, uint8_t* dst, uint8_t* tmp1,
+                    uint8_t* tmp2, int32_t W, int32_t H, int32_t T, const uint8_t* and_not);
+void launch_sources(hipStream_t st, DevLevel L);
+void launch_fill_nnf(hipStream_t st, int2* nnf, uint8_t* nvox, int32_t V);
+void launch_fill_u64(hipStream_t st, unsigned long long* p, int32_t n);
+
+void launch_s0(hipStream_t st, DevLevel L, const PassArgs& A);
+void launch_pass(hipStream_t st, DevLevel L, const PassArgs& A);
+void launch_copy_targets(hipStream_t st, const int32_t* tlist, int32_t nS, const int2* src,
+                         int2* dst);
+
+void launch_recon(hipStream_t st, DevLevel L, const int32_t* plist, int32_t nP,
+                  const uint8_t* filt_excl, int mode, float* out_f, unsigned long long* absdiff);
+void launch_upsample(hipStream_t st, DevLevel F, DevLevel C, const int32_t* ftlist,
+                     int32_t nS);
+
+void launch_erode3(hipStream_t st, const uint8_t* Hp, uint8_t* E, uint8_t* bd, int32_t W,
+                   int32_t H, int32_t T);
+
+void launch_get_state(hipStream_t st, DevLevel L, uint8_t* rgbt, int32_t* cand, int32_t* dist,
+                      uint8_t* nvox);
+void launch_set_state(hipStream_t st, DevLevel L, const uint8_t* rgbt, const int32_t* cand,
+                      const int32_t* dist, const uint8_t* nvox, unsigned long long* bad);
+void launch_out_rgb(hipStream_t st, DevLevel L0, uint8_t* out);
+
+// stream compaction (stable): out[k] = i for the k-th i with flags[i] != 0
+size_t compact_temp_bytes(int32_t n);
+hipError_t compact(hipStream_t st, const uint8_t* flags, int32_t n, int32_t* out,
+                   int32_t* d_count, void* temp, size_t temp_bytes);
+
+}  // namespace vi

@@ -1,0 +1,942 @@
+// vi_kernels.hip -- gfx950 kernels of the inpainting hot path.
+//
+// Paper anchors (Newson et al., "Video Inpainting of Complex Scenes"):
+//   patch distance           Sec. 2 Eq. (2.2), Sec. 3.3, Sec. 3.5 Eq. (3.9)
+//   ANN search               Sec. 3.1, Alg. 1, Eq. (3.1)
+//   reconstruction           Sec. 3.2 Eqs. (3.2)-(3.4), Sec. 3.3 Eq. (3.8)
+//   pyramids and features    Sec. 3.3 Eqs. (3.5), (3.7), Sec. 3.6, Alg. 4
+//   onion peel               Sec. 3.5, Alg. 3
+//
+// The distance is a gather over 125 voxels, not a dense contraction, so it
+// runs on the VALU: the squared difference is expanded as |a|^2 + |b|^2 -
+// 2 a.b with v_dot4_u32_u8 on packed bytes, exact in uint32 arithmetic
+// because every partial sum is a true partial SSD below 2^31.
+#include <hipcub/hipcub.hpp>
+
+#include "vi_internal.h"
+
+namespace vi {
+
+static constexpr int kBlock = 256;
+
+__device__ __forceinline__ uint32_t dot4(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_udot4(a, b, c, false);
+}
+
+__device__ __forceinline__ void unlin(const DevLevel& L, int32_t p, int32_t& x, int32_t& y,
+                                      int32_t& t) {
+  t = (int32_t)fdiv((uint32_t)p, L.fdWH);
+  int32_t r = p - t * L.WH;
+  y = (int32_t)fdiv((uint32_t)r, L.fdW);
+  x = r - y * L.W;
+}
+
+// ------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+// ------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                              uint64_t k0, uint64_t k1, uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    uint64_t n0 = hi1 ^ c1 ^ k0;
+    uint64_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+// uniform integer in [0, n) from the high 32 bits of w
+__device__ __forceinline__ int32_t draw_below(uint64_t w, uint32_t n) {
+  return (int32_t)(((w >> 32) * (uint64_t)n) >> 32);
+}
+
+// ------------------------------------------------------------------------
+// Patch distance of the target patch at p against the candidate centre c (a
+// source of D~, so every candidate voxel is in the volume and known).  Target
+// voxels outside the volume, or flagged in `excl`, are not compared; `nvox`
+// receives the number compared.
+//
+// Per voxel: |a-b|^2 = a.a + b.b - 2 a.b on the colour word and on the
+// texture word with v_dot4_u32_u8; every partial sum equals the true partial
+// SSD (a sum of non-negative terms below 2^31), exact in uint32.  Frames are
+// visited centre first (dt = 0, -1, +1, -2, +2); after each frame the partial
+// sum is compared with `abort_above` and the evaluation stops early when it
+// exceeds it: the full distance could then only be larger, so the caller's
+// decision is unchanged.  The returned value is the full distance when it is
+// <= abort_above, otherwise some value > abort_above.
+// ------------------------------------------------------------------------
+template <bool MASKED>
+__device__ __forceinline__ uint32_t patch_ssd(const DevLevel& L, const uint8_t* __restrict__ excl,
+                                              int32_t p, int32_t px, int32_t py, int32_t pt,
+                                              int32_t c, uint32_t abort_above, int32_t& nvox) {
+  uint32_t sc = 0, st = 0;  // colour and texture parts, as a.a + b.b - 2 a.b
+  int32_t n = 0;
+  const uint2* __restrict__ vox = L.vox;
+  const uint32_t lam = (uint32_t)L.lambda;
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    const int dt = (f & 1) ? -((f + 1) >> 1) : (f >> 1);  // 0, -1, 1, -2, 2
+    const int32_t tt = pt + dt;
+    if (tt < 0 || tt >= L.T) continue;
+    for (int dy = -2; dy <= 2; ++dy) {
+      const int32_t yy = py + dy;
+      if (yy < 0 || yy >= L.H) continue;
+      const int32_t row = (dt * L.H + dy) * L.W;
+      const uint2* __restrict__ ar = vox + (p + row);
+      const uint2* __restrict__ br = vox + (c + row);
+#pragma unroll
+      for (int dx = -2; dx <= 2; ++dx) {
+        const int32_t xx = px + dx;
+        bool ok = xx >= 0 && xx < L.W;
+        if (MASKED) ok = ok && !excl[p + row + dx];
+        if (!ok) continue;
+        const uint2 a = ar[dx];
+        const uint2 b = br[dx];
+        ++n;
+        sc = dot4(a.x, a.x, sc);
+        sc = dot4(b.x, b.x, sc);
+        st = dot4(a.y, a.y, st);
+        st = dot4(b.y, b.y, st);
+        sc -= 2u * dot4(a.x, b.x, 0u);
+        st -= 2u * dot4(a.y, b.y, 0u);
+      }
+    }
+    if (f < 4 && sc + lam * st > abort_above) break;
+  }
+  nvox = n;
+  return sc + lam * st;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ void count_evals(unsigned long long* evals, int n) {
+  if (!evals) return;
+  unsigned long long s = wave_sum_u64((unsigned long long)n);
+  if ((threadIdx.x & 63) == 0 && s) atomicAdd(evals, s);
+}
+
+// ------------------------------------------------------------------------
+// Step 0 of the search: random initialisation of targets whose match is
+// missing or not a source (Philox purpose 1), then the distance of every
+// target's match on the current video.
+// ------------------------------------------------------------------------
+template <bool MASKED>
+__global__ __launch_bounds__(kBlock) void k_s0(DevLevel L, PassArgs A) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  int ne = 0;
+  if (i < A.nS) {
+    const int32_t p = A.tlist[i];
+    int32_t px, py, pt;
+    unlin(L, p, px, py, pt);
+    int2* nnf = const_cast<int2*>(A.nin);
+    int32_t c = nnf[p].x;
+    if (c < 0 || c >= L.V || !L.dsrc[c]) {
+      uint64_t w[4];
+      philox4x64_10((uint64_t)p, A.step, 0, ((uint64_t)L.level << 8) | 1u, L.seed, 0, w);
+      c = L.dlist[draw_below(w[0], (uint32_t)L.nD)];
+    }
+    int32_t n;
+    const uint32_t d = patch_ssd<MASKED>(L, A.excl, p, px, py, pt, c, 0xffffffffu, n);
+    nnf[p] = make_int2(c, (int32_t)d);
+    L.nvox[p] = (uint8_t)n;
+    ne = 1;
+  }
+  count_evals(A.evals, ne);
+}
+
+// Block index -> logical block such that the workgroups that land on one XCD
+// (dispatch is round-robin over the 8 XCDs) process one contiguous range of
+// targets, which share candidate voxels and neighbour entries in that XCD's L2.
+__device__ __forceinline__ int32_t xcd_block(int32_t b, int32_t nb) {
+  constexpr int32_t kXcd = 8;
+  const int32_t x = b % kXcd, y = b / kXcd;
+  const int32_t q = nb / kXcd, r = nb % kXcd;
+  return x * q + (x < r ? x : r) + y;
+}
+
+__device__ __forceinline__ int lane_prefix(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// ------------------------------------------------------------------------
+// One Jacobi propagation pass at stride s (candidate i = 1..6 is the shift of
+// the neighbour p -/+ s along x, y, t, applied at p), followed, when rs_k > 0,
+// by the random search of iteration rs_k (Eq. (3.1)).  The new match
+// minimises (distance, candidate index); a candidate equal to the incumbent
+// or to an earlier candidate cannot win and is not evaluated.
+//
+// The candidate of neighbour q = p + d is c = cand(q) - d.  cand(q) is a
+// source, so its coordinates lie in [2, dim-3]; for |d| <= 4 a shifted
+// coordinate outside the volume wraps, in linear order, onto a coordinate in
+// {0, 1, dim-2, dim-1} of an adjacent row or frame, or out of [0, V), none of
+// which is a source: the linear test 0 <= c < V && dsrc[c] is therefore the
+// exact vector test.
+//
+// A workgroup of 256 targets works in three phases: (1) each thread gathers
+// its target's candidates and appends (target, direction) entries to an LDS
+// queue, grouped per wave and direction so that neighbouring entries point
+// at neighbouring voxels; (2) all threads evaluate the queue densely and
+// fold (distance << 3 | index) into the target's LDS minimum with a 64-bit
+// atomic min, which is exactly the lexicographic (distance, index) order;
+// (3) each thread takes its target's winner and runs the random search.
+// ------------------------------------------------------------------------
+template <bool MASKED>
+__global__ __launch_bounds__(kBlock) void k_pass(DevLevel L, PassArgs A) {
+  __shared__ int32_t s_p[kBlock];
+  __shared__ int32_t s_xy[kBlock];
+  __shared__ int32_t s_t[kBlock];
+  __shared__ unsigned long long s_best[kBlock];
+  __shared__ int32_t s_cand[kBlock * 6];
+  __shared__ uint16_t s_q[kBlock * 6];
+  __shared__ int32_t s_nq;
+  const int tid = threadIdx.x;
+  const int32_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int32_t i = blk * kBlock + tid;
+  const bool active = i < A.nS;
+  int32_t p = 0, px = 0, py = 0, pt = 0;
+  int2 inc = make_int2(0, 0);
+  if (tid == 0) s_nq = 0;
+  if (active) {
+    p = A.tlist[i];
+    unlin(L, p, px, py, pt);
+    inc = A.nin[p];
+    s_best[tid] = (unsigned long long)(uint32_t)inc.y << 3;
+  }
+  s_p[tid] = p;
+  s_xy[tid] = px | (py << 16);
+  s_t[tid] = pt;
+  __syncthreads();
+  int ne = 0;
+  if (A.s > 0) {
+    const int32_t s = A.s;
+    int32_t c[6];
+    bool v[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int axis = j >> 1;
+      const int32_t sgn = (j & 1) ? 1 : -1;
+      const int32_t coord = axis == 0 ? px : (axis == 1 ? py : pt);
+      const int32_t dim = axis == 0 ? L.W : (axis == 1 ? L.H : L.T);
+      const int32_t stride = axis == 0 ? 1 : (axis == 1 ? L.W : L.WH);
+      const int32_t qc = coord + sgn * s;
+      // nothing beats a perfect incumbent: (0, index 0) is the minimum
+      bool ok = active && inc.y != 0 && qc >= 0 && qc < dim;
+      const int32_t q = p + sgn * s * stride;
+      int32_t cand = -1;
+      if (ok) ok = A.smask[q] != 0;
+      if (ok) {
+        cand = A.nin[q].x - sgn * s * stride;
+        ok = cand >= 0 && cand < L.V && L.dsrc[cand] && cand != inc.x;
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (k < j) ok = ok && !(v[k] && c[k] == cand);
+      c[j] = cand;
+      v[j] = ok;
+      s_cand[tid * 6 + j] = cand;
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const uint64_t bal = __ballot(v[j]);
+      const int cnt = __popcll(bal);
+      int base = 0;
+      if ((tid & 63) == 0 && cnt) base = atomicAdd(&s_nq, cnt);
+      base = __shfl(base, 0);
+      if (v[j]) s_q[base + lane_prefix(bal)] = (uint16_t)(tid | (j << 8));
+    }
+    __syncthreads();
+    const int32_t nq = s_nq;
+    for (int32_t e = tid; e < nq; e += kBlock) {
+      const uint32_t ent = s_q[e];
+      const int lt = ent & 255, j = ent >> 8;
+      const int32_t xy = s_xy[lt];
+      // a candidate whose partial distance exceeds the current best cannot win
+      const uint32_t bound = (uint32_t)(s_best[lt] >> 3);
+      int32_t n;
+      const uint32_t d = patch_ssd<MASKED>(L, A.excl, s_p[lt], xy & 0xFFFF, xy >> 16, s_t[lt],
+                                           s_cand[lt * 6 + j], bound, n);
+      if (d <= bound)
+        atomicMin(&s_best[lt], ((unsigned long long)d << 3) | (unsigned long long)(j + 1));
+    }
+    if (tid == 0) ne += nq;
+    __syncthreads();
+  }
+  if (active) {
+    const unsigned long long key = s_best[tid];
+    const int slot = (int)(key & 7);
+    uint32_t best_d = (uint32_t)(key >> 3);
+    int32_t best_c = slot ? s_cand[tid * 6 + slot - 1] : inc.x;
+    if (A.rs_k > 0) {
+      int32_t cx, cy, ct;
+      unlin(L, best_c, cx, cy, ct);
+      const int32_t R = A.R;
+      const int32_t lox = max(2, cx - R), hix = min(L.W - 3, cx + R);
+      const int32_t loy = max(2, cy - R), hiy = min(L.H - 3, cy + R);
+      const int32_t lot = max(2, ct - R), hit = min(L.T - 3, ct + R);
+      uint64_t w[4];
+      philox4x64_10((uint64_t)p, A.step, (uint64_t)A.rs_k, ((uint64_t)L.level << 8) | 0u, L.seed,
+                    0, w);
+      const int32_t rx = lox + draw_below(w[0], (uint32_t)(hix - lox + 1));
+      const int32_t ry = loy + draw_below(w[1], (uint32_t)(hiy - loy + 1));
+      const int32_t rt = lot + draw_below(w[2], (uint32_t)(hit - lot + 1));
+      const int32_t rc = (rt * L.H + ry) * L.W + rx;
+      // strictly better only: nothing beats distance 0
+      const int nr = (best_d != 0 && rc != best_c && L.dsrc[rc]) ? 1 : 0;
+      if (nr) {
+        int32_t n;
+        const uint32_t d = patch_ssd<MASKED>(L, A.excl, p, px, py, pt, rc, best_d - 1u, n);
+        if (d < best_d) {
+          best_d = d;
+          best_c = rc;
+        }
+      }
+      ne += nr;
+    }
+    A.nout[p] = make_int2(best_c, (int32_t)best_d);
+  }
+  count_evals(A.evals, ne);
+}
+
+__global__ void k_copy_targets(const int32_t* tlist, int32_t nS, const int2* src, int2* dst) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < nS) dst[tlist[i]] = src[tlist[i]];
+}
+
+// ------------------------------------------------------------------------
+// Reconstruction, one wavefront per hole pixel p (Sec. 3.2).  Lane l holds
+// the contributors with offset index l and l + 64 (offsets enumerated
+// dt-major, then dy, then dx): q = p - o votes u(cand(q) + o).
+// delta_q = dist(q) / nvox(q) is ordered through its correctly rounded
+// double, which is exact for ordering: distinct such fractions (numerators
+// < 2^31, denominators <= 125) differ by more than the double spacing.
+// WEIGHTED: sigma^2 is the ceil(3m/4)-th smallest delta (nearest rank),
+// selected by radix walks with wave ballots (float32 keys, then exact keys
+// when a float value is shared by different deltas); weights
+// exp(-delta_q / (2 sigma^2)) with the ratio formed as one double division of
+// exact integer products, then float32.  BEST: (delta, offset index) argmin.
+// ------------------------------------------------------------------------
+template <int MODE, bool FILT>
+__global__ __launch_bounds__(kBlock) void k_recon(DevLevel L, const int32_t* __restrict__ plist,
+                                                  int32_t nP, const uint8_t* __restrict__ excl,
+                                                  float* __restrict__ out_f,
+                                                  unsigned long long* __restrict__ absdiff) {
+  const int lane = threadIdx.x & 63;
+  const int32_t nwaves = gridDim.x * (kBlock / 64);
+  int32_t w = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  unsigned long long my_abs = 0;
+  for (; w < nP; w += nwaves) {
+    const int32_t p = plist[w];
+    int32_t px, py, pt;
+    unlin(L, p, px, py, pt);
+    bool valid[2];
+    int32_t dist[2], nv[2], oi[2];
+    uint64_t key[2];
+    uint2 v[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int32_t o = lane + 64 * k;
+      oi[k] = o;
+      const int32_t dx = o % 5 - 2, dy = (o / 5) % 5 - 2, dt = o / 25 - 2;
+      const int32_t qx = px - dx, qy = py - dy, qt = pt - dt;
+      bool ok = o < 125 && qx >= 0 && qy >= 0 && qt >= 0 && qx < L.W && qy < L.H && qt < L.T;
+      const int32_t q = (qt * L.H + qy) * L.W + qx;
+      if (FILT && ok) ok = !excl[q];
+      valid[k] = ok;
+      key[k] = ~0ull;
+      dist[k] = 0;
+      nv[k] = 1;
+      v[k] = make_uint2(0, 0);
+      if (ok) {
+        const int2 nn = L.nnf0[q];
+        dist[k] = nn.y;
+        nv[k] = L.nvox[q];
+        const double dl = (double)nn.y / (double)nv[k];
+        key[k] = (uint64_t)__double_as_longlong(dl);
+        v[k] = L.vox[nn.x + (dt * L.H + dy) * L.W + dx];
+      }
+    }
+    float s[2] = {0.f, 0.f};
+    int best_lane = 0, best_k = 0;
+    if (MODE == 2) {
+      // argmin of (delta, offset index): keys are exact, indices unique
+      uint64_t bk = key[0];
+      int32_t bo = oi[0];
+      int bkk = 0;
+      if (valid[1] && (key[1] < bk || !valid[0])) {
+        bk = key[1];
+        bo = oi[1];
+        bkk = 1;
+      }
+      if (!valid[0] && !valid[1]) bo = 1 << 20;
+      uint64_t gk = bk;
+      int32_t go = bo;
+      for (int off = 32; off >= 1; off >>= 1) {
+        const uint64_t ok2 = __shfl_xor(gk, off);
+        const int32_t oo = __shfl_xor(go, off);
+        if (ok2 < gk || (ok2 == gk && oo < go)) {
+          gk = ok2;
+          go = oo;
+        }
+      }
+      best_lane = go & 63;
+      best_k = go >> 6;
+      (void)bkk;
+    } else if (MODE == 1) {
+      s[0] = valid[0] ? 1.f : 0.f;
+      s[1] = valid[1] ? 1.f : 0.f;
+    } else {
+      const uint64_t b0 = __ballot(valid[0]), b1 = __ballot(valid[1]);
+      const int m = __popcll(b0) + __popcll(b1);
+      int rr = (3 * m + 3) >> 2;  // 1-based rank
+      // (1) radix walk over the float32 rounding of delta: rounding is
+      // monotone, so the rr-th smallest float key is the rounding of the
+      // rr-th smallest delta; rr ends as the rank inside that float's group
+      uint32_t fk[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        fk[k] = valid[k] ? __float_as_uint((float)__longlong_as_double((long long)key[k])) : 0u;
+      uint32_t fpre = 0, fmask = 0x80000000u;
+      for (int b = 30; b >= 0; --b) {
+        const uint32_t bit = 1u << b;
+        const bool z0 = valid[0] && ((fk[0] & fmask) == fpre) && !(fk[0] & bit);
+        const bool z1 = valid[1] && ((fk[1] & fmask) == fpre) && !(fk[1] & bit);
+        const int cnt = __popcll(__ballot(z0)) + __popcll(__ballot(z1));
+        if (rr > cnt) {
+          rr -= cnt;
+          fpre |= bit;
+        }
+        fmask |= bit;
+      }
+      // (2) inside the group the exact keys are almost always all equal; if
+      // not, finish with a radix walk over the exact 64-bit keys of the group
+      const bool g0 = valid[0] && fk[0] == fpre;
+      const bool g1 = valid[1] && fk[1] == fpre;
+      uint64_t kmin = ~0ull, kmax = 0;
+      if (g0) {
+        kmin = key[0];
+        kmax = key[0];
+      }
+      if (g1) {
+        kmin = key[1] < kmin ? key[1] : kmin;
+        kmax = key[1] > kmax ? key[1] : kmax;
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        const uint64_t a = __shfl_xor(kmin, off), bb = __shfl_xor(kmax, off);
+        kmin = a < kmin ? a : kmin;
+        kmax = bb > kmax ? bb : kmax;
+      }
+      uint64_t prefix = kmin;
+      if (kmin != kmax) {
+        uint64_t pre = 0, mask = 0;
+        for (int b = 63; b >= 0; --b) {
+          const uint64_t bit = 1ull << b;
+          const bool z0 = g0 && ((key[0] & mask) == pre) && !(key[0] & bit);
+          const bool z1 = g1 && ((key[1] & mask) == pre) && !(key[1] & bit);
+          const int cnt = __popcll(__ballot(z0)) + __popcll(__ballot(z1));
+          if (rr > cnt) {
+            rr -= cnt;
+            pre |= bit;
+          }
+          mask |= bit;
+        }
+        prefix = pre;
+      }
+      // a contributor holding the selected key provides (dist_r, n_r)
+      const bool h0 = valid[0] && key[0] == prefix;
+      const bool h1 = valid[1] && key[1] == prefix;
+      const uint64_t hb0 = __ballot(h0), hb1 = __ballot(h1);
+      const int src_lane = hb0 ? (__ffsll((unsigned long long)hb0) - 1)
+                               : (__ffsll((unsigned long long)hb1) - 1);
+      const int src_k = hb0 ? 0 : 1;
+      const int32_t my_d = src_k == 0 ? dist[0] : dist[1];
+      const int32_t my_n = src_k == 0 ? nv[0] : nv[1];
+      const int32_t dr = __shfl(my_d, src_lane);
+      const int32_t nr = __shfl(my_n, src_lane);
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        if (!valid[k]) continue;
+        if (dr > 0) {
+          const double num = (double)((int64_t)dist[k] * (int64_t)nr);
+          const double den = (double)(2 * (int64_t)dr * (int64_t)nv[k]);
+          const float tq = (float)(num / den);
+          s[k] = expf(-tq);
+        } else {
+          s[k] = dist[k] == 0 ? 1.f : 0.f;
+        }
+      }
+    }
+    uint2 oldv = make_uint2(0, 0);
+    if (lane == 0) oldv = L.vox[p];
+    uint32_t nx, ny;
+    if (MODE == 2) {
+      const uint32_t vx0 = __shfl(best_k ? v[1].x : v[0].x, best_lane);
+      const uint32_t vy0 = __shfl(best_k ? v[1].y : v[0].y, best_lane);
+      nx = vx0;
+      ny = vy0;
+      if (lane == 0 && out_f) {
+        float* o = out_f + 5 * (size_t)w;
+        o[0] = (float)(nx & 255) / 255.f;
+        o[1] = (float)((nx >> 8) & 255) / 255.f;
+        o[2] = (float)((nx >> 16) & 255) / 255.f;
+        o[3] = (float)(ny & 255) / 255.f;
+        o[4] = (float)((ny >> 8) & 255) / 255.f;
+      }
+    } else {
+      float acc[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc[c] = 0.f;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const float sk = s[k];
+        acc[0] = fmaf(sk, (float)(v[k].x & 255), acc[0]);
+        acc[1] = fmaf(sk, (float)((v[k].x >> 8) & 255), acc[1]);
+        acc[2] = fmaf(sk, (float)((v[k].x >> 16) & 255), acc[2]);
+        acc[3] = fmaf(sk, (float)(v[k].y & 255), acc[3]);
+        acc[4] = fmaf(sk, (float)((v[k].y >> 8) & 255), acc[4]);
+        acc[5] += sk;
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[c] += __shfl_xor(acc[c], off);
+      }
+      uint32_t q8[5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        const float o = acc[c] / acc[5];
+        const int qi = (int)floorf(o + 0.5f);
+        q8[c] = (uint32_t)(qi > 255 ? 255 : qi);
+        if (lane == 0 && out_f) out_f[5 * (size_t)w + c] = o / 255.f;
+      }
+      nx = q8[0] | (q8[1] << 8) | (q8[2] << 16);
+      ny = q8[3] | (q8[4] << 8);
+    }
+    if (lane == 0) {
+      L.vox[p] = make_uint2(nx, ny);
+      int a = 0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int nvv = (int)((nx >> (8 * c)) & 255), ov = (int)((oldv.x >> (8 * c)) & 255);
+        a += nvv > ov ? nvv - ov : ov - nvv;
+      }
+      my_abs += (unsigned long long)a;
+    }
+  }
+  if (absdiff && lane == 0 && my_abs) atomicAdd(absdiff, my_abs);
+}
+
+// ------------------------------------------------------------------------
+// Level transition (Sec. 3.6): fine target p takes its parent's shift with
+// the spatial components doubled and the parent's distance and count.
+// ------------------------------------------------------------------------
+__global__ void k_upsample(DevLevel F, DevLevel C, const int32_t* __restrict__ ftlist,
+                           int32_t nS) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nS) return;
+  const int32_t p = ftlist[i];
+  int32_t x, y, t;
+  unlin(F, p, x, y, t);
+  const int32_t P = (t * C.H + (y >> 1)) * C.W + (x >> 1);
+  const int2 pc = C.nnf0[P];
+  int32_t cx, cy, ct;
+  unlin(C, pc.x, cx, cy, ct);
+  const int32_t fx = x + 2 * (cx - (x >> 1));
+  const int32_t fy = y + 2 * (cy - (y >> 1));
+  F.nnf0[p] = make_int2((ct * F.H + fy) * F.W + fx, pc.y);
+  F.nvox[p] = C.nvox[P];
+}
+
+// ------------------------------------------------------------------------
+// Pyramids and texture features.
+// ------------------------------------------------------------------------
+__global__ void k_init_level0(const uint8_t* __restrict__ rgb, const uint8_t* __restrict__ mask,
+                              DevLevel L) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.V) return;
+  const bool h = mask[i] != 0;
+  L.hole[i] = h ? 1 : 0;
+  uint32_t x = 0;
+  if (!h) x = (uint32_t)rgb[3 * (size_t)i] | ((uint32_t)rgb[3 * (size_t)i + 1] << 8) |
+              ((uint32_t)rgb[3 * (size_t)i + 2] << 16);
+  L.vox[i] = make_uint2(x, 0);
+}
+
+// 2x2 spatial box mean rounded half up (no temporal subsampling), OR-pooled hole
+__global__ void k_pyr_down(DevLevel F, DevLevel C) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= C.V) return;
+  int32_t x, y, t;
+  unlin(C, i, x, y, t);
+  int any = 0, cnt = 0;
+  uint32_t sr = 0, sg = 0, sb = 0;
+  for (int by = 0; by < 2; ++by)
+    for (int bx = 0; bx < 2; ++bx) {
+      const int32_t fx = 2 * x + bx, fy = 2 * y + by;
+      if (fx >= F.W || fy >= F.H) continue;
+      const int32_t j = (t * F.H + fy) * F.W + fx;
+      any |= F.hole[j];
+      ++cnt;
+      const uint32_t v = F.vox[j].x;
+      sr += v & 255;
+      sg += (v >> 8) & 255;
+      sb += (v >> 16) & 255;
+    }
+  C.hole[i] = (uint8_t)any;
+  uint32_t out = 0;
+  if (!any) {
+    const uint32_t h = (uint32_t)cnt / 2;
+    out = ((sr + h) / cnt) | (((sg + h) / cnt) << 8) | (((sb + h) / cnt) << 16);
+  }
+  C.vox[i] = make_uint2(out, 0);
+}
+
+// |grey(x+1) - grey(x-1)| (times 3) over known pixels, packed:
+// bits 0-9 gx, bit 10 gx defined, bits 11-20 gy, bit 21 gy defined
+__global__ void k_grad(const uint8_t* __restrict__ rgb, DevLevel L, uint32_t* __restrict__ gpk) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.V) return;
+  int32_t x, y, t;
+  unlin(L, i, x, y, t);
+  auto g = [&](int32_t j) -> int {
+    return (int)rgb[3 * (size_t)j] + (int)rgb[3 * (size_t)j + 1] + (int)rgb[3 * (size_t)j + 2];
+  };
+  uint32_t out = 0;
+  if (x >= 1 && x + 1 < L.W && !L.hole[i - 1] && !L.hole[i + 1]) {
+    const int d = g(i + 1) - g(i - 1);
+    out |= (uint32_t)(d < 0 ? -d : d) | (1u << 10);
+  }
+  if (y >= 1 && y + 1 < L.H && !L.hole[i - L.W] && !L.hole[i + L.W]) {
+    const int d = g(i + L.W) - g(i - L.W);
+    out |= ((uint32_t)(d < 0 ? -d : d) << 11) | (1u << 21);
+  }
+  gpk[i] = out;
+}
+
+// sums over [x, x+s) of the defined derivatives: .x = gx sum | count << 20
+__global__ void k_box_h(const uint32_t* __restrict__ gpk, DevLevel L, int32_t s,
+                        uint2* __restrict__ hsum) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.V) return;
+  int32_t x, y, t;
+  unlin(L, i, x, y, t);
+  uint32_t sx = 0, cx = 0, sy = 0, cy = 0;
+  const int32_t e = min(L.W, x + s);
+  for (int32_t xx = x; xx < e; ++xx) {
+    const uint32_t g = gpk[i + (xx - x)];
+    if (g & (1u << 10)) {
+      sx += g & 1023u;
+      ++cx;
+    }
+    if (g & (1u << 21)) {
+      sy += (g >> 11) & 1023u;
+      ++cy;
+    }
+  }
+  hsum[i] = make_uint2(sx | (cx << 20), sy | (cy << 20));
+}
+
+// texture of level l: T(2^l X, 2^l Y, t) of the finest level, rounded half up
+// mean of |grey difference| = S / (3c); zero inside the level's hole
+__global__ void k_tex_level(const uint2* __restrict__ hsum, DevLevel L0, DevLevel Ll, int32_t l,
+                            int32_t s) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= Ll.V) return;
+  uint32_t tx = 0, ty = 0;
+  if (!Ll.hole[i]) {
+    int32_t X, Y, t;
+    unlin(Ll, i, X, Y, t);
+    const int32_t x = X << l, y = Y << l;
+    uint64_t sx = 0, cx = 0, sy = 0, cy = 0;
+    const int32_t e = min(L0.H, y + s);
+    for (int32_t yy = y; yy < e; ++yy) {
+      const uint2 h = hsum[(t * L0.H + yy) * L0.W + x];
+      sx += h.x & 0xFFFFFu;
+      cx += h.x >> 20;
+      sy += h.y & 0xFFFFFu;
+      cy += h.y >> 20;
+    }
+    tx = cx ? (uint32_t)((2 * sx + 3 * cx) / (6 * cx)) : 0;
+    ty = cy ? (uint32_t)((2 * sy + 3 * cy) / (6 * cy)) : 0;
+  }
+  Ll.vox[i].y = tx | (ty << 8);
+}
+
+// ------------------------------------------------------------------------
+// Morphology.
+// ------------------------------------------------------------------------
+// 1-D OR over [-2, 2] along an axis (stride, coordinate extent)
+__global__ void k_dil_axis(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst, int32_t W,
+                           int32_t H, int32_t T, int axis, const uint8_t* __restrict__ and_not) {
+  const int32_t V = W * H * T;
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= V) return;
+  const int32_t x = i % W, y = (i / W) % H, t = i / (W * H);
+  const int32_t c = axis == 0 ? x : (axis == 1 ? y : t);
+  const int32_t dim = axis == 0 ? W : (axis == 1 ? H : T);
+  const int32_t stride = axis == 0 ? 1 : (axis == 1 ? W : W * H);
+  uint8_t r = 0;
+  for (int d = -2; d <= 2; ++d) {
+    const int32_t cc = c + d;
+    if (cc < 0 || cc >= dim) continue;
+    r |= src[i + d * stride];
+  }
+  if (and_not) r = (uint8_t)(r && !and_not[i]);
+  dst[i] = r ? 1 : 0;
+}
+
+// D~: patch inside the volume and no hole voxel in it
+__global__ void k_sources(DevLevel L) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.V) return;
+  int32_t x, y, t;
+  unlin(L, i, x, y, t);
+  const bool inner = x >= 2 && y >= 2 && t >= 2 && x < L.W - 2 && y < L.H - 2 && t < L.T - 2;
+  L.dsrc[i] = (uint8_t)(inner && !L.htil[i]);
+}
+
+// E = H' minus voxels with an in-volume 3x3x3 neighbour outside H'
+// (outside the volume counts as occluded); bd = H' \ E.
+__global__ void k_erode3(const uint8_t* __restrict__ Hp, uint8_t* __restrict__ E,
+                         uint8_t* __restrict__ bd, int32_t W, int32_t H, int32_t T) {
+  const int32_t V = W * H * T;
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= V) return;
+  const int32_t x = i % W, y = (i / W) % H, t = i / (W * H);
+  uint8_t e = 0;
+  if (Hp[i]) {
+    e = 1;
+    for (int dt = -1; dt <= 1; ++dt)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int32_t xx = x + dx, yy = y + dy, tt = t + dt;
+          if (xx < 0 || yy < 0 || tt < 0 || xx >= W || yy >= H || tt >= T) continue;
+          if (!Hp[(tt * H + yy) * W + xx]) e = 0;
+        }
+  }
+  E[i] = e;
+  bd[i] = (uint8_t)(Hp[i] && !e);
+}
+
+// ------------------------------------------------------------------------
+// State transfer and fills.
+// ------------------------------------------------------------------------
+__global__ void k_fill_nnf(int2* nnf, uint8_t* nvox, int32_t V) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= V) return;
+  nnf[i] = make_int2(-1, -1);
+  if (nvox) nvox[i] = 0;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int32_t n) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void k_get_state(DevLevel L, uint8_t* rgbt, int32_t* cand, int32_t* dist,
+                            uint8_t* nvox) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.V) return;
+  if (rgbt) {
+    const uint2 v = L.vox[i];
+    uint8_t* o = rgbt + 5 * (size_t)i;
+    o[0] = v.x & 255;
+    o[1] = (v.x >> 8) & 255;
+    o[2] = (v.x >> 16) & 255;
+    o[3] = v.y & 255;
+    o[4] = (v.y >> 8) & 255;
+  }
+  const bool tg = L.htil[i] != 0;
+  const int2 nn = L.nnf0[i];
+  if (cand) cand[i] = tg ? nn.x : -1;
+  if (dist) dist[i] = tg ? nn.y : -1;
+  if (nvox) nvox[i] = tg ? L.nvox[i] : 0;
+}
+
+// bad[0]: cand outside [-1, V); bad[1]: target without a source match or
+// with a zero voxel count
+__global__ void k_set_state(DevLevel L, const uint8_t* rgbt, const int32_t* cand,
+                            const int32_t* dist, const uint8_t* nvox, unsigned long long* bad) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  int b0 = 0, b1 = 0;
+  if (i < L.V) {
+    if (rgbt && L.hole[i]) {
+      const uint8_t* s = rgbt + 5 * (size_t)i;
+      L.vox[i] = make_uint2((uint32_t)s[0] | ((uint32_t)s[1] << 8) | ((uint32_t)s[2] << 16),
+                            (uint32_t)s[3] | ((uint32_t)s[4] << 8));
+    }
+    const bool tg = L.htil[i] != 0;
+    int2 nn = L.nnf0[i];
+    if (cand) {
+      const int32_t c = cand[i];
+      if (c < -1 || c >= L.V) b0 = 1;
+      nn.x = tg ? c : -1;
+      if (tg && (c < 0 || c >= L.V || !L.dsrc[c])) b1 = 1;
+    }
+    if (dist) nn.y = tg ? dist[i] : -1;
+    L.nnf0[i] = nn;
+    if (nvox) {
+      L.nvox[i] = tg ? nvox[i] : 0;
+      if (tg && nvox[i] == 0) b1 = 1;
+    }
+  }
+  unsigned long long s0 = wave_sum_u64((unsigned long long)b0);
+  unsigned long long s1 = wave_sum_u64((unsigned long long)b1);
+  if ((threadIdx.x & 63) == 0) {
+    if (s0) atomicAdd(&bad[0], s0);
+    if (s1) atomicAdd(&bad[1], s1);
+  }
+}
+
+__global__ void k_out_rgb(DevLevel L, uint8_t* out) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.V) return;
+  const uint32_t v = L.vox[i].x;
+  out[3 * (size_t)i] = v & 255;
+  out[3 * (size_t)i + 1] = (v >> 8) & 255;
+  out[3 * (size_t)i + 2] = (v >> 16) & 255;
+}
+
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+static inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
+
+void launch_init_level0(hipStream_t st, const uint8_t* rgb, const uint8_t* mask, DevLevel L0) {
+  k_init_level0<<<grid_for(L0.V), kBlock, 0, st>>>(rgb, mask, L0);
+}
+
+void launch_pyr_down(hipStream_t st, DevLevel F, DevLevel C) {
+  k_pyr_down<<<grid_for(C.V), kBlock, 0, st>>>(F, C);
+}
+
+void launch_texture(hipStream_t st, const uint8_t* rgb, DevLevel L0, int32_t s, uint32_t* gpk,
+                    uint2* hsum) {
+  k_grad<<<grid_for(L0.V), kBlock, 0, st>>>(rgb, L0, gpk);
+  k_box_h<<<grid_for(L0.V), kBlock, 0, st>>>(gpk, L0, s, hsum);
+}
+
+void launch_texture_level(hipStream_t st, const uint2* hsum, DevLevel L0, DevLevel Ll, int32_t l,
+                          int32_t s) {
+  k_tex_level<<<grid_for(Ll.V), kBlock, 0, st>>>(hsum, L0, Ll, l, s);
+}
+
+void launch_dilate5(hipStream_t st, const uint8_t* src, uint8_t* dst, uint8_t* tmp1,
+                    uint8_t* tmp2, int32_t W, int32_t H, int32_t T, const uint8_t* and_not) {
+  const int64_t V = (int64_t)W * H * T;
+  k_dil_axis<<<grid_for(V), kBlock, 0, st>>>(src, tmp1, W, H, T, 0, nullptr);
+  k_dil_axis<<<grid_for(V), kBlock, 0, st>>>(tmp1, tmp2, W, H, T, 1, nullptr);
+  k_dil_axis<<<grid_for(V), kBlock, 0, st>>>(tmp2, dst, W, H, T, 2, and_not);
+}
+
+void launch_sources(hipStream_t st, DevLevel L) { k_sources<<<grid_for(L.V), kBlock, 0, st>>>(L); }
+
+
+void launch_fill_nnf(hipStream_t st, int2* nnf, uint8_t* nvox, int32_t V) {
+  k_fill_nnf<<<grid_for(V), kBlock, 0, st>>>(nnf, nvox, V);
+}
+
+void launch_fill_u64(hipStream_t st, unsigned long long* p, int32_t n) {
+  k_fill_u64<<<grid_for(n), kBlock, 0, st>>>(p, n);
+}
+
+void launch_s0(hipStream_t st, DevLevel L, const PassArgs& A) {
+  if (A.nS <= 0) return;
+  if (A.excl)
+    k_s0<true><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
+  else
+    k_s0<false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
+}
+
+void launch_pass(hipStream_t st, DevLevel L, const PassArgs& A) {
+  if (A.nS <= 0) return;
+  if (A.excl)
+    k_pass<true><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
+  else
+    k_pass<false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
+}
+
+void launch_copy_targets(hipStream_t st, const int32_t* tlist, int32_t nS, const int2* src,
+                         int2* dst) {
+  if (nS <= 0) return;
+  k_copy_targets<<<grid_for(nS), kBlock, 0, st>>>(tlist, nS, src, dst);
+}
+
+void launch_recon(hipStream_t st, DevLevel L, const int32_t* plist, int32_t nP,
+                  const uint8_t* filt_excl, int mode, float* out_f, unsigned long long* absdiff) {
+  if (nP <= 0) return;
+  const int wpb = kBlock / 64;
+  int64_t blocks = (nP + wpb - 1) / wpb;
+  if (blocks > 8192) blocks = 8192;
+  const dim3 g((unsigned)blocks);
+  if (filt_excl) {
+    if (mode == 0)
+      k_recon<0, true><<<g, kBlock, 0, st>>>(L, plist, nP, filt_excl, out_f, absdiff);
+    else if (mode == 1)
+      k_recon<1, true><<<g, kBlock, 0, st>>>(L, plist, nP, filt_excl, out_f, absdiff);
+    else
+      k_recon<2, true><<<g, kBlock, 0, st>>>(L, plist, nP, filt_excl, out_f, absdiff);
+  } else {
+    if (mode == 0)
+      k_recon<0, false><<<g, kBlock, 0, st>>>(L, plist, nP, nullptr, out_f, absdiff);
+    else if (mode == 1)
+      k_recon<1, false><<<g, kBlock, 0, st>>>(L, plist, nP, nullptr, out_f, absdiff);
+    else
+      k_recon<2, false><<<g, kBlock, 0, st>>>(L, plist, nP, nullptr, out_f, absdiff);
+  }
+}
+
+void launch_upsample(hipStream_t st, DevLevel F, DevLevel C, const int32_t* ftlist, int32_t nS) {
+  if (nS <= 0) return;
+  k_upsample<<<grid_for(nS), kBlock, 0, st>>>(F, C, ftlist, nS);
+}
+
+void launch_erode3(hipStream_t st, const uint8_t* Hp, uint8_t* E, uint8_t* bd, int32_t W,
+                   int32_t H, int32_t T) {
+  k_erode3<<<grid_for((int64_t)W * H * T), kBlock, 0, st>>>(Hp, E, bd, W, H, T);
+}
+
+void launch_get_state(hipStream_t st, DevLevel L, uint8_t* rgbt, int32_t* cand, int32_t* dist,
+                      uint8_t* nvox) {
+  k_get_state<<<grid_for(L.V), kBlock, 0, st>>>(L, rgbt, cand, dist, nvox);
+}
+
+void launch_set_state(hipStream_t st, DevLevel L, const uint8_t* rgbt, const int32_t* cand,
+                      const int32_t* dist, const uint8_t* nvox, unsigned long long* bad) {
+  k_set_state<<<grid_for(L.V), kBlock, 0, st>>>(L, rgbt, cand, dist, nvox, bad);
+}
+
+void launch_out_rgb(hipStream_t st, DevLevel L0, uint8_t* out) {
+  k_out_rgb<<<grid_for(L0.V), kBlock, 0, st>>>(L0, out);
+}
+
+size_t compact_temp_bytes(int32_t n) {
+  size_t bytes = 0;
+  hipcub::CountingInputIterator<int32_t> it(0);
+  (void)hipcub::DeviceSelect::Flagged(nullptr, bytes, it, (const uint8_t*)nullptr, (int32_t*)nullptr,
+                                (int32_t*)nullptr, n);
+  return bytes;
+}
+
+hipError_t compact(hipStream_t st, const uint8_t* flags, int32_t n, int32_t* out, int32_t* d_count,
+                   void* temp, size_t temp_bytes) {
+  hipcub::CountingInputIterator<int32_t> it(0);
+  return hipcub::DeviceSelect::Flagged(temp, temp_bytes, it, flags, out, d_count, n, st);
+}
+
+}  // namespace vi

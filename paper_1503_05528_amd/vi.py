@@ -1,0 +1,278 @@
+"""ctypes binding of libvi (include/vi.h): argument marshalling only.
+
+Device buffers are torch tensors on the GPU; every step of the method runs
+in libvi's HIP kernels.  Loading fails loudly when libvi.so is missing: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvi.so")
+
+WEIGHTED, MEAN, BEST = 0, 1, 2
+STATUS = {0: "VI_OK", -1: "VI_E_INVAL", -2: "VI_E_NOMEM", -3: "VI_E_HIP", -4: "VI_E_STATE",
+          -5: "VI_E_EMPTY_SOURCE", -6: "VI_E_BUDGET"}
+
+_LIB = None
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int32),
+        ("patch", C.c_int32 * 3),
+        ("levels", C.c_int32),
+        ("lambda_", C.c_int32),
+        ("pm_iters", C.c_int32),
+        ("n_jf", C.c_int32),
+        ("jf_steps", C.c_int32 * 8),
+        ("rho", C.c_double),
+        ("em_max_iters", C.c_int32),
+        ("em_tol", C.c_double),
+        ("recon_mode", C.c_int32),
+        ("seed", C.c_uint64),
+    ]
+
+
+class ViError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+# exported symbols and their (restype, argtypes)
+_vp, _i32, _i64, _u64, _f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+SIGNATURES = {
+    "vi_params_default": (_i32, [C.c_void_p]),
+    "vi_create": (_i32, [C.POINTER(_vp), C.c_void_p, _i32, _i32, _i32, _vp, _vp, _vp]),
+    "vi_level_info": (_i32, [_vp, _i32, C.POINTER(_i32), C.POINTER(_i64)]),
+    "vi_level_sets": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "vi_nnf_search": (_i32, [_vp, _i32, _i32]),
+    "vi_reconstruct": (_i32, [_vp, _i32, _i32, _vp, _vp]),
+    "vi_inpaint_level": (_i32, [_vp, _i32, C.POINTER(_i32)]),
+    "vi_onion_init": (_i32, [_vp, C.POINTER(_i32)]),
+    "vi_transition": (_i32, [_vp, _i32]),
+    "vi_inpaint": (_i32, [_vp, _vp]),
+    "vi_get_state": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "vi_set_state": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "vi_footprint_bytes": (C.c_size_t, [C.c_void_p, _i32, _i32, _i32, _f64]),
+    "vi_ctx_bytes": (C.c_size_t, [_vp]),
+    "vi_set_stream": (_i32, [_vp, _vp]),
+    "vi_destroy": (None, [_vp]),
+    "vi_last_error": (C.c_char_p, []),
+    "vi_nominal_evals": (_i64, [_vp, _i32]),
+    "vi_get_counters": (_i32, [_vp, _vp]),
+    "vi_reset_counters": (_i32, [_vp]),
+    "vi_profile": (_i32, [_vp, _i32]),
+    "vi_profile_read": (_i32, [_vp, _vp, _i32]),
+}
+
+
+class Counters(C.Structure):
+    _fields_ = [("nominal_evals", C.c_int64), ("effective_evals", C.c_int64),
+                ("searches", C.c_int64), ("em_iters", C.c_int64), ("recon_pixels", C.c_int64)]
+
+
+class KernelTime(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("level", C.c_int32), ("units", C.c_int64),
+                ("ms", C.c_float)]
+
+
+KERNEL_KINDS = {0: "init", 1: "pass", 2: "recon", 3: "other", 4: "onion"}
+
+
+def lib():
+    """Loads libvi.so (built by paper_1503_05528_amd/build.py)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libvi.so not found at {LIB_PATH}: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(fn, st):
+    if st != 0:
+        raise ViError(fn, st, lib().vi_last_error().decode())
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    _check("vi_params_default", lib().vi_params_default(C.byref(p)))
+    for k, v in kw.items():
+        if k == "jf_steps":
+            p.n_jf = len(v)
+            for i, s in enumerate(v):
+                p.jf_steps[i] = s
+        elif k == "patch":
+            for i, s in enumerate(v):
+                p.patch[i] = s
+        elif k == "lam":
+            p.lambda_ = v
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def footprint_bytes(params: Params, W, H, T, hole_fraction) -> int:
+    return int(lib().vi_footprint_bytes(C.byref(params), W, H, T, float(hole_fraction)))
+
+
+class Clip:
+    """One clip's device state in libvi.
+
+    video: uint8 tensor [T][H][W][3] on the GPU; mask: uint8 [T][H][W]."""
+
+    def __init__(self, video: torch.Tensor, mask: torch.Tensor, params: Params | None = None,
+                 stream: torch.cuda.Stream | None = None, **kw):
+        self.params = params if params is not None else default_params(**kw)
+        assert video.dtype == torch.uint8 and mask.dtype == torch.uint8
+        T, H, W, ch = video.shape
+        assert ch == 3 and tuple(mask.shape) == (T, H, W)
+        self.W, self.H, self.T = W, H, T
+        self.device = video.device
+        self.stream = stream
+        video = video.contiguous()
+        mask = mask.contiguous()
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib().vi_create(C.byref(h), C.byref(self.params), W, H, T, _ptr(video),
+                                 _ptr(mask), _stream_handle(stream))
+        _check("vi_create", st)
+        self.h = h
+        self._abs = torch.zeros(1, dtype=torch.int64, device=self.device)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check("vi_set_stream", lib().vi_set_stream(self.h, _stream_handle(stream)))
+
+    @property
+    def levels(self):
+        return self.params.levels
+
+    def info(self, level):
+        d = (C.c_int32 * 3)()
+        c = (C.c_int64 * 3)()
+        _check("vi_level_info", lib().vi_level_info(self.h, level, d, c))
+        return tuple(d), tuple(c)
+
+    def dims(self, level):
+        return self.info(level)[0]
+
+    def nbytes(self):
+        return int(lib().vi_ctx_bytes(self.h))
+
+    def _new(self, shape, dtype):
+        return torch.empty(shape, dtype=dtype, device=self.device)
+
+    def sets(self, level):
+        W, H, T = self.dims(level)
+        hole, dsrc, htil = (self._new((T, H, W), torch.uint8) for _ in range(3))
+        _check("vi_level_sets", lib().vi_level_sets(self.h, level, _ptr(hole), _ptr(dsrc),
+                                                    _ptr(htil)))
+        return hole, dsrc, htil
+
+    def get_state(self, level):
+        W, H, T = self.dims(level)
+        rgbt = self._new((T, H, W, 5), torch.uint8)
+        cand = self._new((T, H, W), torch.int32)
+        dist = self._new((T, H, W), torch.int32)
+        nvox = self._new((T, H, W), torch.uint8)
+        _check("vi_get_state", lib().vi_get_state(self.h, level, _ptr(rgbt), _ptr(cand),
+                                                  _ptr(dist), _ptr(nvox)))
+        return rgbt, cand, dist, nvox
+
+    def set_state(self, level, rgbt=None, cand=None, dist=None, nvox=None):
+        def dev(a, dt):
+            if a is None:
+                return None
+            t = torch.as_tensor(a)
+            return t.to(device=self.device, dtype=dt).contiguous()
+        rgbt, cand, dist, nvox = (dev(rgbt, torch.uint8), dev(cand, torch.int32),
+                                  dev(dist, torch.int32), dev(nvox, torch.uint8))
+        _check("vi_set_state", lib().vi_set_state(self.h, level, _ptr(rgbt), _ptr(cand),
+                                                  _ptr(dist), _ptr(nvox)))
+
+    def nnf_search(self, level, em_iter=0):
+        _check("vi_nnf_search", lib().vi_nnf_search(self.h, level, em_iter))
+
+    def reconstruct(self, level, mode=WEIGHTED, want_out=True):
+        (_, _, _), (nH, _, _) = self.info(level)
+        out = self._new((nH, 5), torch.float32) if want_out else None
+        _check("vi_reconstruct", lib().vi_reconstruct(self.h, level, mode, _ptr(out),
+                                                      _ptr(self._abs)))
+        return out, self._abs
+
+    def inpaint_level(self, level):
+        k = C.c_int32(0)
+        _check("vi_inpaint_level", lib().vi_inpaint_level(self.h, level, C.byref(k)))
+        return int(k.value)
+
+    def onion_init(self):
+        k = C.c_int32(0)
+        _check("vi_onion_init", lib().vi_onion_init(self.h, C.byref(k)))
+        return int(k.value)
+
+    def transition(self, level):
+        _check("vi_transition", lib().vi_transition(self.h, level))
+
+    def inpaint(self, out: torch.Tensor | None = None):
+        if out is None:
+            out = self._new((self.T, self.H, self.W, 3), torch.uint8)
+        _check("vi_inpaint", lib().vi_inpaint(self.h, _ptr(out)))
+        return out
+
+    def nominal_evals(self, level):
+        return int(lib().vi_nominal_evals(self.h, level))
+
+    def counters(self) -> dict:
+        c = Counters()
+        _check("vi_get_counters", lib().vi_get_counters(self.h, C.byref(c)))
+        return {k: int(getattr(c, k)) for k, _ in Counters._fields_}
+
+    def reset_counters(self):
+        _check("vi_reset_counters", lib().vi_reset_counters(self.h))
+
+    def profile(self, on: bool = True):
+        _check("vi_profile", lib().vi_profile(self.h, 1 if on else 0))
+
+    def profile_read(self, cap: int = 1 << 16):
+        buf = (KernelTime * cap)()
+        n = lib().vi_profile_read(self.h, buf, cap)
+        if n < 0:
+            _check("vi_profile_read", n)
+        return [(KERNEL_KINDS[buf[i].kind], buf[i].level, int(buf[i].units), float(buf[i].ms))
+                for i in range(n)]
