@@ -138,6 +138,10 @@ def main():
         d["launches"] += 1
         d["units"] += units
         d["ms"] += ms
+    by_level = {}
+    for kind, lvl, units, ms in recs:
+        key = f"{kind}@L{lvl}"
+        by_level[key] = round(by_level.get(key, 0.0) + ms / a.steps, 3)
     pas = kinds.get("pass", {"launches": 1, "units": 0, "ms": 1.0})
     avg_ms = pas["ms"] / pas["launches"]
     bytes_per_launch = BYTES_PER_EVAL * pas["units"] / pas["launches"]
@@ -171,6 +175,7 @@ def main():
         "latency_p99_ms": 1000 * max(lat),
         "effective_evals_per_s": effective / elapsed,
         "kernel_ms_per_step": {k: round(v["ms"] / a.steps, 3) for k, v in kinds.items()},
+        "kernel_ms_per_step_by_level": by_level,
         "roofline": roofline,
         "cpu_baseline": None,
     }

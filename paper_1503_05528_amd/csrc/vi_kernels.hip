@@ -70,53 +70,130 @@ __device__ __forceinline__ int32_t draw_below(uint64_t w, uint32_t n) {
 //
 // Per voxel: |a-b|^2 = a.a + b.b - 2 a.b on the colour word and on the
 // texture word with v_dot4_u32_u8; every partial sum equals the true partial
-// SSD (a sum of non-negative terms below 2^31), exact in uint32.  Frames are
-// visited centre first (dt = 0, -1, +1, -2, +2); after each frame the partial
-// sum is compared with `abort_above` and the evaluation stops early when it
-// exceeds it: the full distance could then only be larger, so the caller's
-// decision is unchanged.  The returned value is the full distance when it is
-// <= abort_above, otherwise some value > abort_above.
+// SSD (a sum of non-negative terms below 2^31), exact in uint32.  The 25 rows
+// (dt, dy) are visited from the centre outwards, the centre row first, then
+// in pairs of rows; after each group the partial sum is compared with `abort_above` and
+// the evaluation stops when it exceeds it: the full distance could then only
+// be larger, so the caller's decision is unchanged, and a hopeless candidate
+// (typically a random-search draw, a cold fetch) costs one row instead of 25.
+// Inside a group every load is unconditional (voxels outside the volume read
+// the patch centre and are masked to zero), so the loads of a group are in
+// flight together instead of one round trip per voxel.  The returned value
+// is the full distance when it is <= abort_above, otherwise some value >
+// abort_above.
 // ------------------------------------------------------------------------
-template <bool MASKED>
-__device__ __forceinline__ uint32_t patch_ssd(const DevLevel& L, const uint8_t* __restrict__ excl,
-                                              int32_t p, int32_t px, int32_t py, int32_t pt,
-                                              int32_t c, uint32_t abort_above, int32_t& nvox) {
-  uint32_t sc = 0, st = 0;  // colour and texture parts, as a.a + b.b - 2 a.b
-  int32_t n = 0;
+__constant__ int8_t kRowDt[25] = {0, 0, 0, -1, 1, 0, 0, -1, -1, 1, 1, -2, 2,
+                                  -1, -1, 1, 1, -2, -2, 2, 2, -2, -2, 2, 2};
+__constant__ int8_t kRowDy[25] = {0, -1, 1, 0, 0, -2, 2, -1, 1, -1, 1, 0, 0,
+                                  -2, 2, -2, 2, -1, 1, -1, 1, -2, 2, -2, 2};
+
+struct SsdAcc {
+  uint32_t sc, st;  // colour and texture partial sums
+  int32_t n;
+};
+
+__device__ __forceinline__ void acc_voxel(SsdAcc& q, uint2 a, uint2 b) {
+  q.sc = dot4(a.x, a.x, q.sc);
+  q.sc = dot4(b.x, b.x, q.sc);
+  q.st = dot4(a.y, a.y, q.st);
+  q.st = dot4(b.y, b.y, q.st);
+  q.sc -= 2u * dot4(a.x, b.x, 0u);
+  q.st -= 2u * dot4(a.y, b.y, 0u);
+}
+
+// rows [R0, R1) of the centre-out order; FULL: every target voxel is in the
+// volume and compared (no masks)
+template <int R0, int R1, bool FULL, bool MASKED>
+__device__ __forceinline__ void ssd_rows(const DevLevel& L, const uint8_t* __restrict__ excl,
+                                         int32_t p, int32_t px, int32_t py, int32_t pt, int32_t c,
+                                         SsdAcc& q) {
   const uint2* __restrict__ vox = L.vox;
-  const uint32_t lam = (uint32_t)L.lambda;
 #pragma unroll
-  for (int f = 0; f < 5; ++f) {
-    const int dt = (f & 1) ? -((f + 1) >> 1) : (f >> 1);  // 0, -1, 1, -2, 2
-    const int32_t tt = pt + dt;
-    if (tt < 0 || tt >= L.T) continue;
-    for (int dy = -2; dy <= 2; ++dy) {
-      const int32_t yy = py + dy;
-      if (yy < 0 || yy >= L.H) continue;
-      const int32_t row = (dt * L.H + dy) * L.W;
-      const uint2* __restrict__ ar = vox + (p + row);
-      const uint2* __restrict__ br = vox + (c + row);
+  for (int r = R0; r < R1; ++r) {
+    const int dt = kRowDt[r], dy = kRowDy[r];
+    const int32_t row = dt * L.WH + dy * L.W;
+    if (FULL) {
+#pragma unroll
+      for (int dx = -2; dx <= 2; ++dx) acc_voxel(q, vox[p + row + dx], vox[c + row + dx]);
+    } else {
+      const int32_t tt = pt + dt, yy = py + dy;
+      const bool rok = tt >= 0 && tt < L.T && yy >= 0 && yy < L.H;
 #pragma unroll
       for (int dx = -2; dx <= 2; ++dx) {
         const int32_t xx = px + dx;
-        bool ok = xx >= 0 && xx < L.W;
-        if (MASKED) ok = ok && !excl[p + row + dx];
-        if (!ok) continue;
-        const uint2 a = ar[dx];
-        const uint2 b = br[dx];
-        ++n;
-        sc = dot4(a.x, a.x, sc);
-        sc = dot4(b.x, b.x, sc);
-        st = dot4(a.y, a.y, st);
-        st = dot4(b.y, b.y, st);
-        sc -= 2u * dot4(a.x, b.x, 0u);
-        st -= 2u * dot4(a.y, b.y, 0u);
+        bool ok = rok && xx >= 0 && xx < L.W;
+        const int32_t ai = ok ? p + row + dx : p;
+        if (MASKED) ok = ok && !excl[ai];
+        uint2 a = vox[ai];
+        uint2 b = vox[c + row + dx];
+        if (!ok) {
+          a = make_uint2(0, 0);
+          b = make_uint2(0, 0);
+        }
+        q.n += ok ? 1 : 0;
+        acc_voxel(q, a, b);
       }
     }
-    if (f < 4 && sc + lam * st > abort_above) break;
   }
-  nvox = n;
-  return sc + lam * st;
+}
+
+template <bool FULL, bool MASKED, bool ABORT>
+__device__ __forceinline__ uint32_t ssd_groups(const DevLevel& L, const uint8_t* excl, int32_t p,
+                                               int32_t px, int32_t py, int32_t pt, int32_t c,
+                                               uint32_t abort_above, int32_t& nvox) {
+  SsdAcc q{0u, 0u, 0};
+  const uint32_t lam = (uint32_t)L.lambda;
+  ssd_rows<0, 1, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
+  if (!ABORT || q.sc + lam * q.st <= abort_above) {
+    ssd_rows<1, 3, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
+    if (!ABORT || q.sc + lam * q.st <= abort_above) {
+      ssd_rows<3, 5, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
+      if (!ABORT || q.sc + lam * q.st <= abort_above) {
+        ssd_rows<5, 7, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
+        if (!ABORT || q.sc + lam * q.st <= abort_above) {
+          ssd_rows<7, 9, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
+          if (!ABORT || q.sc + lam * q.st <= abort_above) {
+            ssd_rows<9, 11, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
+            if (!ABORT || q.sc + lam * q.st <= abort_above) {
+              ssd_rows<11, 13, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
+              if (!ABORT || q.sc + lam * q.st <= abort_above) {
+                ssd_rows<13, 15, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
+                if (!ABORT || q.sc + lam * q.st <= abort_above) {
+                  ssd_rows<15, 17, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
+                  if (!ABORT || q.sc + lam * q.st <= abort_above) {
+                    ssd_rows<17, 19, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
+                    if (!ABORT || q.sc + lam * q.st <= abort_above) {
+                      ssd_rows<19, 21, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
+                      if (!ABORT || q.sc + lam * q.st <= abort_above) {
+                        ssd_rows<21, 23, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
+                        if (!ABORT || q.sc + lam * q.st <= abort_above) {
+                          ssd_rows<23, 25, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
+                        }
+                      }
+                    }
+                  }
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  nvox = FULL ? 125 : q.n;
+  return q.sc + lam * q.st;
+}
+
+template <bool MASKED, bool ABORT>
+__device__ __forceinline__ uint32_t patch_ssd(const DevLevel& L, const uint8_t* __restrict__ excl,
+                                              int32_t p, int32_t px, int32_t py, int32_t pt,
+                                              int32_t c, uint32_t abort_above, int32_t& nvox) {
+  const bool interior = !MASKED && px >= 2 && py >= 2 && pt >= 2 && px < L.W - 2 &&
+                        py < L.H - 2 && pt < L.T - 2;
+  // wave-uniform choice: a whole wave of interior targets needs no masks
+  if (__all(interior))
+    return ssd_groups<true, MASKED, ABORT>(L, excl, p, px, py, pt, c, abort_above, nvox);
+  return ssd_groups<false, MASKED, ABORT>(L, excl, p, px, py, pt, c, abort_above, nvox);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
@@ -151,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_s0(DevLevel L, PassArgs A) {
       c = L.dlist[draw_below(w[0], (uint32_t)L.nD)];
     }
     int32_t n;
-    const uint32_t d = patch_ssd<MASKED>(L, A.excl, p, px, py, pt, c, 0xffffffffu, n);
+    const uint32_t d = patch_ssd<MASKED, false>(L, A.excl, p, px, py, pt, c, 0xffffffffu, n);
     nnf[p] = make_int2(c, (int32_t)d);
     L.nvox[p] = (uint8_t)n;
     ne = 1;
@@ -227,6 +304,10 @@ __global__ __launch_bounds__(kBlock) void k_pass(DevLevel L, PassArgs A) {
     const int32_t s = A.s;
     int32_t c[6];
     bool v[6];
+    int32_t qi[6];
+    bool qok[6];
+    // every load of the gather is unconditional (clamped to p), so the six
+    // neighbour entries, then the six source flags, are fetched together
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       const int axis = j >> 1;
@@ -236,20 +317,38 @@ __global__ __launch_bounds__(kBlock) void k_pass(DevLevel L, PassArgs A) {
       const int32_t stride = axis == 0 ? 1 : (axis == 1 ? L.W : L.WH);
       const int32_t qc = coord + sgn * s;
       // nothing beats a perfect incumbent: (0, index 0) is the minimum
-      bool ok = active && inc.y != 0 && qc >= 0 && qc < dim;
-      const int32_t q = p + sgn * s * stride;
-      int32_t cand = -1;
-      if (ok) ok = A.smask[q] != 0;
-      if (ok) {
-        cand = A.nin[q].x - sgn * s * stride;
-        ok = cand >= 0 && cand < L.V && L.dsrc[cand] && cand != inc.x;
-      }
+      qok[j] = active && inc.y != 0 && qc >= 0 && qc < dim;
+      qi[j] = qok[j] ? p + sgn * s * stride : p;
+    }
+    int32_t cq[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) cq[j] = A.nin[qi[j]].x;
+    if (MASKED) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) qok[j] = qok[j] && A.smask[qi[j]] != 0;
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int axis = j >> 1;
+      const int32_t sgn = (j & 1) ? 1 : -1;
+      const int32_t stride = axis == 0 ? 1 : (axis == 1 ? L.W : L.WH);
+      // unmasked search: the target set is H~, where every entry holds a
+      // match after step 0 and every other entry holds -1 in both buffers
+      if (!MASKED) qok[j] = qok[j] && cq[j] >= 0;
+      c[j] = cq[j] - sgn * s * stride;
+      qok[j] = qok[j] && c[j] >= 0 && c[j] < L.V;
+    }
+    uint8_t ds[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) ds[j] = L.dsrc[qok[j] ? c[j] : 0];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      bool ok = qok[j] && ds[j] && c[j] != inc.x;
 #pragma unroll
       for (int k = 0; k < 6; ++k)
-        if (k < j) ok = ok && !(v[k] && c[k] == cand);
-      c[j] = cand;
+        if (k < j) ok = ok && !(v[k] && c[k] == c[j]);
       v[j] = ok;
-      s_cand[tid * 6 + j] = cand;
+      s_cand[tid * 6 + j] = c[j];
     }
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
@@ -269,8 +368,8 @@ __global__ __launch_bounds__(kBlock) void k_pass(DevLevel L, PassArgs A) {
       // a candidate whose partial distance exceeds the current best cannot win
       const uint32_t bound = (uint32_t)(s_best[lt] >> 3);
       int32_t n;
-      const uint32_t d = patch_ssd<MASKED>(L, A.excl, s_p[lt], xy & 0xFFFF, xy >> 16, s_t[lt],
-                                           s_cand[lt * 6 + j], bound, n);
+      const uint32_t d = patch_ssd<MASKED, true>(L, A.excl, s_p[lt], xy & 0xFFFF, xy >> 16,
+                                                 s_t[lt], s_cand[lt * 6 + j], bound, n);
       if (d <= bound)
         atomicMin(&s_best[lt], ((unsigned long long)d << 3) | (unsigned long long)(j + 1));
     }
@@ -300,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(DevLevel L, PassArgs A) {
       const int nr = (best_d != 0 && rc != best_c && L.dsrc[rc]) ? 1 : 0;
       if (nr) {
         int32_t n;
-        const uint32_t d = patch_ssd<MASKED>(L, A.excl, p, px, py, pt, rc, best_d - 1u, n);
+        const uint32_t d = patch_ssd<MASKED, true>(L, A.excl, p, px, py, pt, rc, best_d - 1u, n);
         if (d < best_d) {
           best_d = d;
           best_c = rc;
@@ -348,28 +447,38 @@ __global__ __launch_bounds__(kBlock) void k_recon(DevLevel L, const int32_t* __r
     int32_t dist[2], nv[2], oi[2];
     uint64_t key[2];
     uint2 v[2];
+    // unconditional loads (an invalid contributor reads the pixel itself and
+    // is masked), so both contributors' entries, then both votes, are
+    // fetched together
+    int32_t qq[2], off[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int32_t o = lane + 64 * k;
       oi[k] = o;
       const int32_t dx = o % 5 - 2, dy = (o / 5) % 5 - 2, dt = o / 25 - 2;
       const int32_t qx = px - dx, qy = py - dy, qt = pt - dt;
-      bool ok = o < 125 && qx >= 0 && qy >= 0 && qt >= 0 && qx < L.W && qy < L.H && qt < L.T;
-      const int32_t q = (qt * L.H + qy) * L.W + qx;
-      if (FILT && ok) ok = !excl[q];
-      valid[k] = ok;
-      key[k] = ~0ull;
-      dist[k] = 0;
-      nv[k] = 1;
-      v[k] = make_uint2(0, 0);
-      if (ok) {
-        const int2 nn = L.nnf0[q];
-        dist[k] = nn.y;
-        nv[k] = L.nvox[q];
-        const double dl = (double)nn.y / (double)nv[k];
-        key[k] = (uint64_t)__double_as_longlong(dl);
-        v[k] = L.vox[nn.x + (dt * L.H + dy) * L.W + dx];
-      }
+      valid[k] = o < 125 && qx >= 0 && qy >= 0 && qt >= 0 && qx < L.W && qy < L.H && qt < L.T;
+      qq[k] = valid[k] ? (qt * L.H + qy) * L.W + qx : p;
+      off[k] = (dt * L.H + dy) * L.W + dx;
+    }
+    int2 nn[2];
+    uint8_t nb[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      nn[k] = L.nnf0[qq[k]];
+      nb[k] = L.nvox[qq[k]];
+      if (FILT) valid[k] = valid[k] && !excl[qq[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      // a masked contributor still needs an in-volume address for its vote
+      const int32_t src = valid[k] ? nn[k].x + off[k] : p;
+      v[k] = L.vox[src];
+      dist[k] = valid[k] ? nn[k].y : 0;
+      nv[k] = valid[k] ? (int32_t)nb[k] : 1;
+      const double dl = (double)dist[k] / (double)nv[k];
+      key[k] = valid[k] ? (uint64_t)__double_as_longlong(dl) : ~0ull;
+      if (!valid[k]) v[k] = make_uint2(0, 0);
     }
     float s[2] = {0.f, 0.f};
     int best_lane = 0, best_k = 0;
