@@ -40,7 +40,148 @@ def parse():
     ap.add_argument("--cpu-level", type=int, default=1)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--batch-clips", type=int, default=64)
+    ap.add_argument("--served-seconds", type=float, default=30.0)
+    ap.add_argument("--served-rate", type=float, default=4.0)
     return ap.parse_args()
+
+
+def _gen_batch_clip(seed):
+    from paper_1503_05528_amd import synth
+    c = synth.batch_clip(seed)
+    return c.occluded_input(), c.mask, c.levels
+
+
+def gen_batch_clips(n, base_seed=1000):
+    """The mixed-size batch workload, generated in worker processes."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(min(16, max(1, os.cpu_count() or 1))) as pool:
+        return pool.map(_gen_batch_clip, [base_seed + i for i in range(n)])
+
+
+def batched_vs_serial(clips, em_iters):
+    """One clip at a time (vi_inpaint) versus all clips in one batch (one
+    graph launch per EM iteration), from inputs resident in HBM to outputs
+    in HBM; outputs must be identical."""
+    import torch
+    from paper_1503_05528_amd import vi
+    dev = [(torch.from_numpy(v).cuda(), torch.from_numpy(m).cuda(), L) for v, m, L in clips]
+    mk = lambda i: vi.default_params(levels=dev[i][2], em_tol=-1.0, em_max_iters=em_iters,
+                                     seed=1000 + i)
+    # warm-up (kernels, allocator)
+    g = vi.Clip(dev[0][0], dev[0][1], params=mk(0))
+    g.inpaint()
+    g.close()
+    torch.cuda.synchronize()
+    serial_out, service = [], []
+    nominal = 0
+    t0 = time.perf_counter()
+    for i, (v, m, L) in enumerate(dev):
+        s0 = time.perf_counter()
+        g = vi.Clip(v, m, params=mk(i))
+        serial_out.append(g.inpaint())
+        nominal += g.counters()["nominal_evals"]
+        g.close()
+        service.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    t_serial = time.perf_counter() - t0
+    b = vi.Batch()
+    # tune once on a throw-away batch of the same clips so the timed run
+    # measures steady-state steps
+    tb = [vi.Clip(v, m, params=mk(i)) for i, (v, m, L) in enumerate(dev)]
+    for g in tb:
+        b.add(g)
+    b.step()
+    tune = b.tune()
+    for g in tb:
+        g.close()
+    b.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = vi.Batch(tune=tune)
+    members = [vi.Clip(v, m, params=mk(i)) for i, (v, m, L) in enumerate(dev)]
+    for g in members:
+        b.add(g)
+    steps = b.run()
+    outs = [g.output() for g in members]
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    same = all(torch.equal(a, c) for a, c in zip(outs, serial_out))
+    for g in members:
+        g.close()
+    b.close()
+    n = len(dev)
+    return {"clips": n, "serial_clips_per_s": n / t_serial, "batched_clips_per_s": n / t_batch,
+            "speedup": t_serial / t_batch, "serial_s": t_serial, "batched_s": t_batch,
+            "batched_steps": steps, "tune": list(tune) if tune else None,
+            "outputs_identical": bool(same), "nominal_evals": nominal,
+            "batched_evals_per_s": nominal / t_batch}, service
+
+
+def served(clips, sd_clip, seconds, rate, em_iters, service_alone):
+    """Poisson arrivals served by the continuous-batching server, against
+    serial FIFO execution of the same trace with the measured per-clip
+    service times."""
+    import threading
+    import torch
+    from paper_1503_05528_amd import synth
+    from paper_1503_05528_amd.serve import GpuEngine, Request, Server, fifo_latencies, percentile
+    trace = synth.served_trace(seconds, rate, seed=2000)
+    rng = __import__("numpy").random.default_rng(7)
+    jobs = []
+    for (t, kind, seed) in trace:
+        if kind == "sd":
+            jobs.append((t, -1))
+        else:
+            jobs.append((t, int(rng.integers(0, len(clips)))))
+    free = torch.cuda.mem_get_info()[0]
+    # two lanes: clips of up to 20 M voxels, and larger ones, overlap on the GPU
+    lanes = [GpuEngine(), GpuEngine()]
+    big = lambda r: 1 if r.mask.size > 20_000_000 else 0
+    srv = Server(lanes, hbm_budget=int(0.8 * free), max_slots=256, route=big)
+
+    def req(idx):
+        if idx < 0:
+            v, m, L = sd_clip
+        else:
+            v, m, L = clips[idx]
+        return Request(v, m, dict(levels=L, em_tol=-1.0, em_max_iters=em_iters, seed=1),
+                       hole_fraction=float(m.mean()))
+    srv.start()
+    t0 = time.perf_counter()
+    futs = []
+
+    def feeder():
+        for (t, idx) in jobs:
+            d = t0 + t - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            r = req(idx)
+            r.arrival = t0 + t
+            futs.append(srv.submit(r))
+    th = threading.Thread(target=feeder)
+    th.start()
+    th.join()
+    for f in futs:
+        f.result()
+    t_end = time.perf_counter()
+    srv.stop()
+    for e in lanes:
+        e.close()
+    st = srv.latency_stats()
+    serial = fifo_latencies([t for t, _ in jobs],
+                            [service_alone[idx] for _, idx in jobs])
+    return {"rate_per_s": rate, "duration_s": seconds, "jobs": len(jobs),
+            "sd_jobs": sum(1 for _, i in jobs if i < 0),
+            "clips_per_s": len(jobs) / (t_end - t0),
+            "p50_s": st.get("p50_s"), "p99_s": st.get("p99_s"),
+            "serial_fifo_p50_s": percentile(serial, 0.5),
+            "serial_fifo_p99_s": percentile(serial, 0.99),
+            "max_running": srv.max_running, "steps": srv.steps,
+            "max_admitted_gb": srv.max_admitted_bytes / 2 ** 30}
 
 
 def make_clip(name):
@@ -179,6 +320,17 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    if not a.no_batched or not a.no_served:
+        bclips = gen_batch_clips(a.batch_clips)
+        bres, service = batched_vs_serial(bclips, a.em_iters)
+        if not a.no_batched:
+            line["batched"] = bres
+        if not a.no_served:
+            # service time of the SD clip alone = this run's SD step latency
+            svc = {i: service[i] for i in range(len(bclips))}
+            svc[-1] = statistics.median(lat)
+            line["served"] = served(bclips, (clip.occluded_input(), clip.mask, levels),
+                                    a.served_seconds, a.served_rate, a.em_iters, svc)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(clip, levels, a.em_iters, a.cpu_level)
     print(json.dumps(line), flush=True)

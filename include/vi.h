@@ -168,6 +168,47 @@ const char* vi_last_error(void);
  * one random candidate per iteration).  Returns -1 on error. */
 int64_t vi_nominal_evals(const vi_ctx* ctx, int32_t level);
 
+/* Output of a finished clip (vi_inpaint done, or finished inside a batch):
+ * out_rgb (dev) [T][H][W][3].  VI_E_STATE before the clip has finished.
+ * Syncs. */
+vi_status vi_output(vi_ctx* ctx, uint8_t* out_rgb);
+/* 1 when the clip has completed the whole algorithm, else 0. */
+int32_t vi_done(const vi_ctx* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Batches.  Many clips of uneven sizes and masks advance together: every
+ * vi_batch_step runs one EM iteration (search + reconstruction, Alg. 4 inner
+ * loop) of every member in the EM phase as ONE captured HIP graph of
+ * persistent kernels over all members' targets and hole pixels; onion peels,
+ * level transitions and final reconstructions of individual members run
+ * between the graph launches.  Each member's result is bit-identical to
+ * vi_inpaint on that clip alone.  Members must share pm_iters and jf_steps
+ * (n_jf >= 1).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t block;     /* targets per workgroup: 64, 128 or 256 */
+  int32_t grid_mult; /* persistent grid = compute units x grid_mult */
+  int32_t tuned;     /* nonzero: use these values; zero: autotune at the first step */
+} vi_tune;
+typedef struct vi_batch vi_batch;
+
+/* tune (host) or NULL: autotune on the first step (times one propagation
+ * pass per candidate shape on the live batch, into scratch buffers).
+ * hip_stream: stream for all batch work, or NULL for a stream of its own
+ * (graph capture cannot use the legacy default stream). */
+vi_status vi_batch_create(vi_batch** out, const vi_tune* tune, void* hip_stream);
+/* Adds a clip that has not finished; its work moves to the batch's stream.
+ * VI_E_BUDGET when the batch holds 1024 clips. */
+vi_status vi_batch_add(vi_batch* b, vi_ctx* ctx);
+vi_status vi_batch_remove(vi_batch* b, vi_ctx* ctx);
+/* One step of every member; n_done (host) receives the number of members
+ * that have finished.  Syncs. */
+vi_status vi_batch_step(vi_batch* b, int32_t* n_done);
+vi_status vi_batch_get_tune(const vi_batch* b, vi_tune* out);
+int32_t vi_batch_size(const vi_batch* b);
+/* Frees the batch (not its members); NULL-safe. */
+void vi_batch_destroy(vi_batch* b);
+
 /* Work counters of a context since creation or the last reset (host out).
  * effective_evals is read back from the device: syncs. */
 typedef struct {

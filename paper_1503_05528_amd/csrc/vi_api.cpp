@@ -77,6 +77,11 @@ struct vi_ctx {
   };
   std::vector<hipEvent_t> events;  // pairs (start, stop)
   std::vector<Rec> recs;
+  // position in Alg. 4 when driven step by step (batches): phase 0 = not
+  // started, 1 = EM loop of cur_level at iteration em_k, 2 = finished
+  int32_t phase = 0;
+  int32_t cur_level = -1;
+  int32_t em_k = 0;
 };
 
 namespace {
@@ -600,10 +605,22 @@ vi_status vi_inpaint(vi_ctx* c, uint8_t* out_rgb) {
   }
   Level& l0 = c->lv[0];
   if (l0.nH > 0) VI_TRY(recon(c, 0, l0.hlist, l0.nH, nullptr, VI_RECON_BEST, nullptr, nullptr));
+  c->phase = 2;
+  c->cur_level = 0;
   vi::launch_out_rgb(c->st, l0.d, out_rgb);
   VI_TRY(launched("output"));
   return sync(c);
 }
+
+vi_status vi_output(vi_ctx* c, uint8_t* out_rgb) {
+  if (!c || !out_rgb) return fail(VI_E_INVAL, "null argument");
+  if (c->phase != 2) return fail(VI_E_STATE, "the clip has not finished");
+  vi::launch_out_rgb(c->st, c->lv[0].d, out_rgb);
+  VI_TRY(launched("output"));
+  return sync(c);
+}
+
+int32_t vi_done(const vi_ctx* c) { return c && c->phase == 2 ? 1 : 0; }
 
 vi_status vi_get_state(const vi_ctx* c, int32_t level, uint8_t* rgbt, int32_t* cand,
                        int32_t* dist, uint8_t* nvox) {
@@ -677,6 +694,408 @@ int32_t vi_profile_read(vi_ctx* c, vi_kernel_time* out, int32_t cap) {
   }
   c->recs.clear();
   return n;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batches: many clips advance together, one EM iteration per step.
+// ===========================================================================
+namespace {
+
+// Alg. 4 driven step by step: start = onion peel of the coarsest level;
+// after the EM loop of a level stops, transition to the next finer level or,
+// at level 0, the final best-patch reconstruction.
+vi_status drive_start(vi_ctx* c) {
+  VI_TRY(onion(c, nullptr));
+  c->phase = 1;
+  c->cur_level = c->L - 1;
+  c->em_k = 0;
+  return VI_OK;
+}
+
+vi_status drive_finish_level(vi_ctx* c) {
+  c->lv[c->cur_level].complete = true;
+  if (c->cur_level > 0) {
+    VI_TRY(transition(c, c->cur_level - 1));
+    c->cur_level -= 1;
+    c->em_k = 0;
+    return VI_OK;
+  }
+  Level& l0 = c->lv[0];
+  if (l0.nH > 0) VI_TRY(recon(c, 0, l0.hlist, l0.nH, nullptr, VI_RECON_BEST, nullptr, nullptr));
+  c->phase = 2;
+  return VI_OK;
+}
+
+// levels without a hole run no EM iteration
+vi_status drive_skip_empty(vi_ctx* c) {
+  while (c->phase == 1 && c->lv[c->cur_level].nH == 0) VI_TRY(drive_finish_level(c));
+  return VI_OK;
+}
+
+bool same_schedule(const vi_params& a, const vi_params& b) {
+  if (a.pm_iters != b.pm_iters || a.n_jf != b.n_jf) return false;
+  for (int i = 0; i < a.n_jf; ++i)
+    if (a.jf_steps[i] != b.jf_steps[i]) return false;
+  return true;
+}
+
+}  // namespace
+
+struct vi_batch {
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  std::vector<vi_ctx*> members;
+  vi_params sched{};  // propagation schedule shared by all members
+  bool have_sched = false;
+  int32_t ncu = 0;
+  // tile configuration
+  int32_t blk = 0, grid_mult = 0;
+  bool tuned = false;
+  // device job table and chunk maps (capacities fixed at creation so that a
+  // captured graph stays valid)
+  int32_t cap_jobs = 0, cap_tchunks = 0, cap_pchunks = 0;
+  vi::JobDesc* d_jobs = nullptr;
+  int32_t* d_tchunk_job = nullptr;
+  int32_t* d_pchunk_job = nullptr;
+  int32_t* d_counts = nullptr;
+  unsigned long long* d_abs = nullptr;
+  unsigned long long* d_scratch = nullptr;
+  int32_t* d_queue = nullptr;
+  std::vector<vi::JobDesc> h_jobs;
+  std::vector<int32_t> h_tj, h_pj;
+  std::vector<vi_ctx*> job_ctx;
+  std::vector<unsigned long long> h_abs;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t steps_run = 0;
+};
+
+namespace {
+
+void batch_free(vi_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  for (void* p : {(void*)b->d_jobs, (void*)b->d_tchunk_job, (void*)b->d_pchunk_job,
+                  (void*)b->d_counts, (void*)b->d_abs, (void*)b->d_scratch, (void*)b->d_queue})
+    if (p) (void)hipFree(p);
+  b->d_queue = nullptr;
+  b->d_jobs = nullptr;
+  b->d_tchunk_job = b->d_pchunk_job = b->d_counts = nullptr;
+  b->d_abs = b->d_scratch = nullptr;
+}
+
+vi_status batch_bail(vi_batch* b, vi_status s) {
+  batch_free(b);
+  return s;
+}
+
+// job table and chunk maps of the members in the EM phase, for a block size
+vi_status batch_build(vi_batch* b, int blk, bool scratch_evals) {
+  b->h_jobs.clear();
+  b->h_tj.clear();
+  b->h_pj.clear();
+  b->job_ctx.clear();
+  for (vi_ctx* c : b->members) {
+    if (c->phase != 1) continue;
+    const Level& lv = c->lv[c->cur_level];
+    vi::JobDesc J{};
+    J.L = lv.d;
+    J.tlist = lv.tlist;
+    J.hlist = lv.hlist;
+    J.nS = lv.nS;
+    J.nH = lv.nH;
+    J.recon_mode = c->prm.recon_mode;
+    J.step = (uint64_t)c->em_k;
+    J.absdiff = b->d_abs + b->h_jobs.size();
+    J.evals = scratch_evals ? b->d_scratch : c->d_u64 + 3;
+    const int32_t rmax = r_max(lv.d);
+    for (int k = 0; k <= vi::kMaxPmIters; ++k) J.R[k] = k == 0 ? 0 : rs_radius(c->prm, rmax, k);
+    J.tchunk0 = (int32_t)b->h_tj.size();
+    J.pchunk0 = (int32_t)b->h_pj.size();
+    const int32_t nt = (lv.nS + blk - 1) / blk;
+    const int32_t np = (lv.nH + vi::kPixChunk - 1) / vi::kPixChunk;
+    const int32_t j = (int32_t)b->h_jobs.size();
+    for (int32_t i = 0; i < nt; ++i) b->h_tj.push_back(j);
+    for (int32_t i = 0; i < np; ++i) b->h_pj.push_back(j);
+    b->h_jobs.push_back(J);
+    b->job_ctx.push_back(c);
+  }
+  if ((int32_t)b->h_jobs.size() > b->cap_jobs)
+    return fail(VI_E_BUDGET, "more clips in the EM phase than the batch holds");
+  if ((int32_t)b->h_tj.size() > b->cap_tchunks || (int32_t)b->h_pj.size() > b->cap_pchunks)
+    return fail(VI_E_BUDGET, "the batch's work lists are full");
+  const int32_t counts[3] = {(int32_t)b->h_tj.size(), (int32_t)b->h_pj.size(),
+                             (int32_t)b->h_jobs.size()};
+  if (!b->h_jobs.empty())
+    VI_HIP(hipMemcpyAsync(b->d_jobs, b->h_jobs.data(), sizeof(vi::JobDesc) * b->h_jobs.size(),
+                          hipMemcpyHostToDevice, b->st));
+  if (!b->h_tj.empty())
+    VI_HIP(hipMemcpyAsync(b->d_tchunk_job, b->h_tj.data(), sizeof(int32_t) * b->h_tj.size(),
+                          hipMemcpyHostToDevice, b->st));
+  if (!b->h_pj.empty())
+    VI_HIP(hipMemcpyAsync(b->d_pchunk_job, b->h_pj.data(), sizeof(int32_t) * b->h_pj.size(),
+                          hipMemcpyHostToDevice, b->st));
+  VI_HIP(hipMemcpyAsync(b->d_counts, counts, sizeof(counts), hipMemcpyHostToDevice, b->st));
+  // pageable sources: complete the copies before the host vectors change
+  VI_HIP(hipStreamSynchronize(b->st));
+  return VI_OK;
+}
+
+vi::BatchArgs batch_args(const vi_batch* b) {
+  vi::BatchArgs B{};
+  B.jobs = b->d_jobs;
+  B.tchunk_job = b->d_tchunk_job;
+  B.pchunk_job = b->d_pchunk_job;
+  B.counts = b->d_counts;
+  B.queue = b->d_queue;
+  return B;
+}
+
+// the launches of one batched EM iteration: step 0, every propagation pass
+// with the random search fused into the last pass of each iteration, the copy
+// back when the pass count is odd, and the reconstruction
+vi_status batch_enqueue_iteration(vi_batch* b) {
+  const vi::BatchArgs B = batch_args(b);
+  const int32_t grid = b->ncu * b->grid_mult;
+  int32_t slot = 0;
+  vi::launch_batch_zero(b->st, B, b->cap_jobs);
+  vi::launch_batch_s0(b->st, B, b->blk, grid, slot++);
+  int parity = 0;
+  for (int k = 1; k <= b->sched.pm_iters; ++k)
+    for (int js = 0; js < b->sched.n_jf; ++js) {
+      vi::launch_batch_pass(b->st, B, b->blk, grid, b->sched.jf_steps[js],
+                            js == b->sched.n_jf - 1 ? k : 0, parity, slot++);
+      parity ^= 1;
+    }
+  if (parity) vi::launch_batch_copy(b->st, B, b->blk, grid, slot++);
+  vi::launch_batch_recon(b->st, B, b->ncu * 8, slot++);
+  return launched("batched iteration");
+}
+
+// Times one propagation pass (reading buffer 0, writing buffer 1, which the
+// next real pass overwrites before reading) for each candidate tile shape
+// and keeps the fastest.  Step 0 is re-run first; it is idempotent for the
+// current state and EM index.
+vi_status batch_autotune(vi_batch* b) {
+  static const int kBlk[3] = {64, 128, 256};
+  static const int kMult[3] = {2, 4, 8};
+  hipEvent_t e0, e1;
+  VI_HIP(hipEventCreate(&e0));
+  VI_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bb = 256, bm = 4;
+  vi_status st = VI_OK;
+  for (int ib = 0; ib < 3 && st == VI_OK; ++ib) {
+    if ((st = batch_build(b, kBlk[ib], true)) != VI_OK) break;
+    const vi::BatchArgs B = batch_args(b);
+    vi::launch_batch_zero(b->st, B, b->cap_jobs);
+    vi::launch_batch_s0(b->st, B, kBlk[ib], b->ncu * 4, 0);
+    for (int im = 0; im < 3; ++im) {
+      const int32_t grid = b->ncu * kMult[im];
+      const int32_t s = b->sched.n_jf > 0 ? b->sched.jf_steps[0] : 1;
+      vi::launch_batch_pass(b->st, B, kBlk[ib], grid, s, 1, 0, 1 + 4 * im);
+      (void)hipEventRecord(e0, b->st);
+      for (int r = 0; r < 3; ++r)
+        vi::launch_batch_pass(b->st, B, kBlk[ib], grid, s, 1, 0, 2 + 4 * im + r);
+      (void)hipEventRecord(e1, b->st);
+      if ((st = launched("autotune")) != VI_OK) break;
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        st = fail(VI_E_HIP, "autotune event");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        bb = kBlk[ib];
+        bm = kMult[im];
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != VI_OK) return st;
+  b->blk = bb;
+  b->grid_mult = bm;
+  b->tuned = true;
+  return VI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vi_status vi_batch_create(vi_batch** out, const vi_tune* tune, void* hip_stream) {
+  if (!out) return fail(VI_E_INVAL, "null output handle");
+  *out = nullptr;
+  if (tune && tune->tuned) {
+    if (tune->block != 64 && tune->block != 128 && tune->block != 256)
+      return fail(VI_E_INVAL, "tune.block must be 64, 128 or 256");
+    if (tune->grid_mult < 1 || tune->grid_mult > 64)
+      return fail(VI_E_INVAL, "tune.grid_mult must be in [1, 64]");
+  }
+  vi_batch* b = new (std::nothrow) vi_batch();
+  if (!b) return fail(VI_E_NOMEM, "host allocation failed");
+  if (hip_stream) {
+    b->st = static_cast<hipStream_t>(hip_stream);
+  } else {
+    // graph capture needs a stream of its own (default priority)
+    if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return fail(VI_E_HIP, "stream creation failed");
+    }
+    b->own_stream = true;
+  }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    vi_batch_destroy(b);
+    return fail(VI_E_HIP, "device query failed");
+  }
+  b->ncu = prop.multiProcessorCount;
+  if (tune && tune->tuned) {
+    b->blk = tune->block;
+    b->grid_mult = tune->grid_mult;
+    b->tuned = true;
+  }
+  b->cap_jobs = 1024;
+  b->cap_tchunks = 1 << 21;
+  b->cap_pchunks = 1 << 21;
+  void* p = nullptr;
+  auto alloc = [&](size_t bytes) -> void* {
+    void* q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return q;
+  };
+  b->d_jobs = static_cast<vi::JobDesc*>(alloc(sizeof(vi::JobDesc) * (size_t)b->cap_jobs));
+  b->d_tchunk_job = static_cast<int32_t*>(alloc(sizeof(int32_t) * (size_t)b->cap_tchunks));
+  b->d_pchunk_job = static_cast<int32_t*>(alloc(sizeof(int32_t) * (size_t)b->cap_pchunks));
+  b->d_counts = static_cast<int32_t*>(alloc(sizeof(int32_t) * 4));
+  b->d_abs = static_cast<unsigned long long*>(alloc(sizeof(unsigned long long) * b->cap_jobs));
+  b->d_scratch = static_cast<unsigned long long*>(alloc(sizeof(unsigned long long) * 8));
+  b->d_queue = static_cast<int32_t*>(alloc(sizeof(int32_t) * vi::kQueueSlots));
+  (void)p;
+  if (!b->d_jobs || !b->d_tchunk_job || !b->d_pchunk_job || !b->d_counts || !b->d_abs ||
+      !b->d_scratch || !b->d_queue) {
+    vi_batch_destroy(b);
+    return fail(VI_E_NOMEM, "batch allocation failed");
+  }
+  const int32_t zero[4] = {0, 0, 0, 0};
+  if (hipMemcpy(b->d_counts, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) {
+    vi_batch_destroy(b);
+    return fail(VI_E_HIP, "batch initialisation failed");
+  }
+  *out = b;
+  return VI_OK;
+}
+
+void vi_batch_destroy(vi_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->st);
+  batch_free(b);
+  if (b->own_stream) (void)hipStreamDestroy(b->st);
+  delete b;
+}
+
+vi_status vi_batch_add(vi_batch* b, vi_ctx* c) {
+  if (!b || !c) return fail(VI_E_INVAL, "null argument");
+  for (vi_ctx* m : b->members)
+    if (m == c) return fail(VI_E_INVAL, "the clip is already in the batch");
+  if (c->prm.n_jf < 1) return fail(VI_E_INVAL, "batched clips need at least one propagation step");
+  if (b->have_sched && !same_schedule(b->sched, c->prm))
+    return fail(VI_E_INVAL, "all clips of a batch share pm_iters and jf_steps");
+  if ((int32_t)b->members.size() >= b->cap_jobs) return fail(VI_E_BUDGET, "the batch is full");
+  if (c->phase == 2) return fail(VI_E_STATE, "the clip has already finished");
+  if (!b->have_sched) {
+    b->sched = c->prm;
+    b->have_sched = true;
+  }
+  // the clip's work is ordered on the batch's stream from now on
+  (void)hipStreamSynchronize(c->st);
+  c->st = b->st;
+  b->members.push_back(c);
+  return VI_OK;
+}
+
+vi_status vi_batch_remove(vi_batch* b, vi_ctx* c) {
+  if (!b || !c) return fail(VI_E_INVAL, "null argument");
+  for (size_t i = 0; i < b->members.size(); ++i)
+    if (b->members[i] == c) {
+      (void)hipStreamSynchronize(b->st);
+      b->members.erase(b->members.begin() + (long)i);
+      return VI_OK;
+    }
+  return fail(VI_E_INVAL, "the clip is not in the batch");
+}
+
+int32_t vi_batch_size(const vi_batch* b) { return b ? (int32_t)b->members.size() : 0; }
+
+vi_status vi_batch_get_tune(const vi_batch* b, vi_tune* out) {
+  if (!b || !out) return fail(VI_E_INVAL, "null argument");
+  out->block = b->blk;
+  out->grid_mult = b->grid_mult;
+  out->tuned = b->tuned ? 1 : 0;
+  return VI_OK;
+}
+
+vi_status vi_batch_step(vi_batch* b, int32_t* n_done) {
+  if (!b) return fail(VI_E_INVAL, "null batch");
+  if (n_done) *n_done = 0;
+  int32_t done = 0;
+  // clips that have not started: onion peel of their coarsest level
+  for (vi_ctx* c : b->members) {
+    if (c->phase == 0) VI_TRY(drive_start(c));
+    VI_TRY(drive_skip_empty(c));
+  }
+  bool any = false;
+  for (vi_ctx* c : b->members) any = any || c->phase == 1;
+  if (any) {
+    if (!b->tuned) VI_TRY(batch_autotune(b));
+    VI_TRY(batch_build(b, b->blk, false));
+    if (!b->exec) {
+      VI_HIP(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+      const vi_status cs = batch_enqueue_iteration(b);
+      hipGraph_t g = nullptr;
+      const hipError_t ce = hipStreamEndCapture(b->st, &g);
+      if (cs != VI_OK) return cs;
+      if (ce != hipSuccess) return fail(VI_E_HIP, std::string("graph capture failed: ") +
+                                                      hipGetErrorString(ce));
+      b->graph = g;
+      VI_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    VI_HIP(hipGraphLaunch(b->exec, b->st));
+    const size_t nj = b->h_jobs.size();
+    b->h_abs.assign(nj, 0);
+    VI_HIP(hipMemcpyAsync(b->h_abs.data(), b->d_abs, sizeof(unsigned long long) * nj,
+                          hipMemcpyDeviceToHost, b->st));
+    VI_HIP(hipStreamSynchronize(b->st));
+    ++b->steps_run;
+    for (size_t j = 0; j < nj; ++j) {
+      vi_ctx* c = b->job_ctx[j];
+      const Level& lv = c->lv[c->cur_level];
+      c->n_nominal += per_target_evals(c->prm, r_max(lv.d)) * (int64_t)lv.nS;
+      c->n_searches += 1;
+      c->n_em += 1;
+      c->n_recon += lv.nH;
+      c->em_k += 1;
+      const double e = (double)b->h_abs[j] / (3.0 * (double)lv.nH);
+      if (!(e > c->prm.em_tol && c->em_k < c->prm.em_max_iters)) {
+        VI_TRY(drive_finish_level(c));
+        VI_TRY(drive_skip_empty(c));
+      }
+    }
+  }
+  for (vi_ctx* c : b->members) done += c->phase == 2 ? 1 : 0;
+  VI_HIP(hipStreamSynchronize(b->st));
+  if (n_done) *n_done = done;
+  return VI_OK;
 }
 
 }  // extern "C"

@@ -70,6 +70,35 @@ struct PassArgs {
   unsigned long long* evals;  // effective-evaluation counter, or null
 };
 
+// One clip's EM iteration inside a batched launch (device memory).
+constexpr int kMaxPmIters = 64;
+struct JobDesc {
+  DevLevel L;
+  const int32_t* tlist;
+  const int32_t* hlist;
+  int32_t nS, nH;
+  int32_t tchunk0;  // first target chunk of this job in the flat chunk list
+  int32_t pchunk0;  // first pixel chunk
+  int32_t recon_mode;
+  int32_t pad_;
+  uint64_t step;    // EM index at the level (Philox counter word 1)
+  unsigned long long* absdiff;
+  unsigned long long* evals;
+  int32_t R[kMaxPmIters + 1];  // random-search radius of iteration k
+};
+
+constexpr int kPixChunk = 64;  // hole pixels per chunk of a batched reconstruction
+
+constexpr int kQueueSlots = 1024;  // chunk counters, one per launch of a batched iteration
+
+struct BatchArgs {
+  const JobDesc* jobs;
+  const int32_t* tchunk_job;  // job of every target chunk
+  const int32_t* pchunk_job;  // job of every pixel chunk
+  const int32_t* counts;      // [0] target chunks, [1] pixel chunks, [2] jobs
+  int32_t* queue;             // [kQueueSlots] next chunk of each launch
+};
+
 // ---------------------------------------------------------------- launchers
 // All launch on `st`; none synchronises.
 void launch_init_level0(hipStream_t st, const uint8_t* rgb, const uint8_t* mask, DevLevel L0);
@@ -103,6 +132,17 @@ void launch_get_state(hipStream_t st, DevLevel L, uint8_t* rgbt, int32_t* cand, 
 void launch_set_state(hipStream_t st, DevLevel L, const uint8_t* rgbt, const int32_t* cand,
                       const int32_t* dist, const uint8_t* nvox, unsigned long long* bad);
 void launch_out_rgb(hipStream_t st, DevLevel L0, uint8_t* out);
+
+// batched, persistent launches over every job's chunks (grid = `grid` blocks;
+// blk = targets per workgroup, 64, 128 or 256)
+// `slot` selects the chunk counter of the launch; launch_batch_zero clears
+// the counters and the per-job outputs at the start of an iteration
+void launch_batch_zero(hipStream_t st, const BatchArgs& B, int32_t max_jobs);
+void launch_batch_s0(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t slot);
+void launch_batch_pass(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t s,
+                       int32_t k, int32_t parity, int32_t slot);
+void launch_batch_copy(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t slot);
+void launch_batch_recon(hipStream_t st, const BatchArgs& B, int32_t grid, int32_t slot);
 
 // stream compaction (stable): out[k] = i for the k-th i with flags[i] != 0
 size_t compact_temp_bytes(int32_t n);

@@ -213,26 +213,28 @@ __device__ __forceinline__ void count_evals(unsigned long long* evals, int n) {
 // target's match on the current video.
 // ------------------------------------------------------------------------
 template <bool MASKED>
-__global__ __launch_bounds__(kBlock) void k_s0(DevLevel L, PassArgs A) {
-  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-  int ne = 0;
-  if (i < A.nS) {
-    const int32_t p = A.tlist[i];
-    int32_t px, py, pt;
-    unlin(L, p, px, py, pt);
-    int2* nnf = const_cast<int2*>(A.nin);
-    int32_t c = nnf[p].x;
-    if (c < 0 || c >= L.V || !L.dsrc[c]) {
-      uint64_t w[4];
-      philox4x64_10((uint64_t)p, A.step, 0, ((uint64_t)L.level << 8) | 1u, L.seed, 0, w);
-      c = L.dlist[draw_below(w[0], (uint32_t)L.nD)];
-    }
-    int32_t n;
-    const uint32_t d = patch_ssd<MASKED, false>(L, A.excl, p, px, py, pt, c, 0xffffffffu, n);
-    nnf[p] = make_int2(c, (int32_t)d);
-    L.nvox[p] = (uint8_t)n;
-    ne = 1;
+__device__ __forceinline__ int s0_target(const DevLevel& L, const PassArgs& A, int32_t i) {
+  if (i >= A.nS) return 0;
+  const int32_t p = A.tlist[i];
+  int32_t px, py, pt;
+  unlin(L, p, px, py, pt);
+  int2* nnf = const_cast<int2*>(A.nin);
+  int32_t c = nnf[p].x;
+  if (c < 0 || c >= L.V || !L.dsrc[c]) {
+    uint64_t w[4];
+    philox4x64_10((uint64_t)p, A.step, 0, ((uint64_t)L.level << 8) | 1u, L.seed, 0, w);
+    c = L.dlist[draw_below(w[0], (uint32_t)L.nD)];
   }
+  int32_t n;
+  const uint32_t d = patch_ssd<MASKED, false>(L, A.excl, p, px, py, pt, c, 0xffffffffu, n);
+  nnf[p] = make_int2(c, (int32_t)d);
+  L.nvox[p] = (uint8_t)n;
+  return 1;
+}
+
+template <bool MASKED>
+__global__ __launch_bounds__(kBlock) void k_s0(DevLevel L, PassArgs A) {
+  const int ne = s0_target<MASKED>(L, A, blockIdx.x * kBlock + threadIdx.x);
   count_evals(A.evals, ne);
 }
 
@@ -273,18 +275,33 @@ __device__ __forceinline__ int lane_prefix(uint64_t mask) {
 // atomic min, which is exactly the lexicographic (distance, index) order;
 // (3) each thread takes its target's winner and runs the random search.
 // ------------------------------------------------------------------------
-template <bool MASKED>
-__global__ __launch_bounds__(kBlock) void k_pass(DevLevel L, PassArgs A) {
-  __shared__ int32_t s_p[kBlock];
-  __shared__ int32_t s_xy[kBlock];
-  __shared__ int32_t s_t[kBlock];
-  __shared__ unsigned long long s_best[kBlock];
-  __shared__ int32_t s_cand[kBlock * 6];
-  __shared__ uint16_t s_q[kBlock * 6];
-  __shared__ int32_t s_nq;
+template <int BLK>
+struct PassShared {
+  int32_t p[BLK];
+  int32_t xy[BLK];
+  int32_t t[BLK];
+  unsigned long long best[BLK];
+  int32_t cand[BLK * 6];
+  uint16_t q[BLK * 6];
+  int32_t nq;
+};
+
+// One block of BLK consecutive targets (block index blk of the target list);
+// returns the evaluations this thread accounts for.  All threads of the
+// workgroup must call it together.
+template <int BLK, bool MASKED>
+__device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, int32_t blk,
+                                          PassShared<BLK>& sh) {
+  int32_t* s_p = sh.p;
+  int32_t* s_xy = sh.xy;
+  int32_t* s_t = sh.t;
+  unsigned long long* s_best = sh.best;
+  int32_t* s_cand = sh.cand;
+  uint16_t* s_q = sh.q;
+  int32_t& s_nq = sh.nq;
   const int tid = threadIdx.x;
-  const int32_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int32_t i = blk * kBlock + tid;
+  const int32_t i = blk * BLK + tid;
+  __syncthreads();  // the previous block's readers are done with the LDS
   const bool active = i < A.nS;
   int32_t p = 0, px = 0, py = 0, pt = 0;
   int2 inc = make_int2(0, 0);
@@ -361,7 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(DevLevel L, PassArgs A) {
     }
     __syncthreads();
     const int32_t nq = s_nq;
-    for (int32_t e = tid; e < nq; e += kBlock) {
+    for (int32_t e = tid; e < nq; e += BLK) {
       const uint32_t ent = s_q[e];
       const int lt = ent & 255, j = ent >> 8;
       const int32_t xy = s_xy[lt];
@@ -409,8 +426,17 @@ __global__ __launch_bounds__(kBlock) void k_pass(DevLevel L, PassArgs A) {
     }
     A.nout[p] = make_int2(best_c, (int32_t)best_d);
   }
+  return ne;
+}
+
+template <bool MASKED>
+__global__ __launch_bounds__(kBlock) void k_pass(DevLevel L, PassArgs A) {
+  __shared__ PassShared<kBlock> sh;
+  const int ne = pass_block<kBlock, MASKED>(L, A, xcd_block(blockIdx.x, gridDim.x), sh);
   count_evals(A.evals, ne);
 }
+
+
 
 __global__ void k_copy_targets(const int32_t* tlist, int32_t nS, const int2* src, int2* dst) {
   const int32_t i = blockIdx.x * kBlock + threadIdx.x;
@@ -430,16 +456,15 @@ __global__ void k_copy_targets(const int32_t* tlist, int32_t nS, const int2* src
 // exp(-delta_q / (2 sigma^2)) with the ratio formed as one double division of
 // exact integer products, then float32.  BEST: (delta, offset index) argmin.
 // ------------------------------------------------------------------------
+// One wavefront reconstructs hole pixel number w of plist; lane 0 adds the
+// pixel's |change| over the colour channels to my_abs.
 template <int MODE, bool FILT>
-__global__ __launch_bounds__(kBlock) void k_recon(DevLevel L, const int32_t* __restrict__ plist,
-                                                  int32_t nP, const uint8_t* __restrict__ excl,
-                                                  float* __restrict__ out_f,
-                                                  unsigned long long* __restrict__ absdiff) {
+__device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __restrict__ plist,
+                                            int32_t w, const uint8_t* __restrict__ excl,
+                                            float* __restrict__ out_f,
+                                            unsigned long long& my_abs) {
   const int lane = threadIdx.x & 63;
-  const int32_t nwaves = gridDim.x * (kBlock / 64);
-  int32_t w = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  unsigned long long my_abs = 0;
-  for (; w < nP; w += nwaves) {
+  {
     const int32_t p = plist[w];
     int32_t px, py, pt;
     unlin(L, p, px, py, pt);
@@ -647,7 +672,112 @@ __global__ __launch_bounds__(kBlock) void k_recon(DevLevel L, const int32_t* __r
       my_abs += (unsigned long long)a;
     }
   }
-  if (absdiff && lane == 0 && my_abs) atomicAdd(absdiff, my_abs);
+}
+
+template <int MODE, bool FILT>
+__global__ __launch_bounds__(kBlock) void k_recon(DevLevel L, const int32_t* __restrict__ plist,
+                                                  int32_t nP, const uint8_t* __restrict__ excl,
+                                                  float* __restrict__ out_f,
+                                                  unsigned long long* __restrict__ absdiff) {
+  const int32_t nwaves = gridDim.x * (kBlock / 64);
+  unsigned long long my_abs = 0;
+  for (int32_t w = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); w < nP; w += nwaves)
+    recon_pixel<MODE, FILT>(L, plist, w, excl, out_f, my_abs);
+  if (absdiff && (threadIdx.x & 63) == 0 && my_abs) atomicAdd(absdiff, my_abs);
+}
+
+
+// ------------------------------------------------------------------------
+// Batched, persistent launches: one launch covers the chunks of every job
+// (clip) in the batch.  A job's chunks are consecutive in the flat list.
+// Workgroups take chunks from a shared counter in increasing order (chunks
+// of different jobs and levels cost very different amounts, so a static
+// split would leave the launch waiting for its slowest workgroup) and run
+// exactly the per-target / per-pixel code of the single-clip kernels, so a
+// clip's results do not depend on the batch it runs in or on which
+// workgroup takes which chunk.  Chunk counts are read from device memory, so
+// a captured graph of these launches stays valid when jobs come and go.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ int32_t next_chunk(int32_t* counter, int32_t& s_c) {
+  __syncthreads();  // every thread has read the previous chunk index
+  if (threadIdx.x == 0) s_c = atomicAdd(counter, 1);
+  __syncthreads();
+  return s_c;
+}
+
+__global__ void kb_zero(BatchArgs B) {
+  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < B.counts[2]) *B.jobs[j].absdiff = 0;
+  if (j < kQueueSlots) B.queue[j] = 0;
+}
+
+template <int BLK>
+__global__ __launch_bounds__(BLK) void kb_s0(BatchArgs B, int32_t slot) {
+  __shared__ int32_t s_c;
+  const int32_t n = B.counts[0];
+  for (int32_t c = next_chunk(B.queue + slot, s_c); c < n; c = next_chunk(B.queue + slot, s_c)) {
+    const JobDesc& J = B.jobs[B.tchunk_job[c]];
+    PassArgs A{};
+    A.tlist = J.tlist;
+    A.nS = J.nS;
+    A.nin = J.L.nnf0;
+    A.step = J.step;
+    const int ne = s0_target<false>(J.L, A, (c - J.tchunk0) * BLK + (int32_t)threadIdx.x);
+    count_evals(J.evals, ne);
+  }
+}
+
+template <int BLK>
+__global__ __launch_bounds__(BLK) void kb_pass(BatchArgs B, int32_t s, int32_t k, int32_t parity,
+                                               int32_t slot) {
+  __shared__ PassShared<BLK> sh;
+  __shared__ int32_t s_c;
+  const int32_t n = B.counts[0];
+  for (int32_t c = next_chunk(B.queue + slot, s_c); c < n; c = next_chunk(B.queue + slot, s_c)) {
+    const JobDesc& J = B.jobs[B.tchunk_job[c]];
+    PassArgs A{};
+    A.tlist = J.tlist;
+    A.nS = J.nS;
+    A.smask = J.L.htil;
+    A.nin = parity ? J.L.nnf1 : J.L.nnf0;
+    A.nout = parity ? J.L.nnf0 : J.L.nnf1;
+    A.s = s;
+    A.R = J.R[k];
+    A.rs_k = (k > 0 && A.R >= 1) ? k : 0;
+    A.step = J.step;
+    const int ne = pass_block<BLK, false>(J.L, A, c - J.tchunk0, sh);
+    count_evals(J.evals, ne);
+  }
+}
+
+template <int BLK>
+__global__ __launch_bounds__(BLK) void kb_copy(BatchArgs B, int32_t slot) {
+  __shared__ int32_t s_c;
+  const int32_t n = B.counts[0];
+  for (int32_t c = next_chunk(B.queue + slot, s_c); c < n; c = next_chunk(B.queue + slot, s_c)) {
+    const JobDesc& J = B.jobs[B.tchunk_job[c]];
+    const int32_t i = (c - J.tchunk0) * BLK + (int32_t)threadIdx.x;
+    if (i < J.nS) J.L.nnf0[J.tlist[i]] = J.L.nnf1[J.tlist[i]];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void kb_recon(BatchArgs B, int32_t slot) {
+  constexpr int kWaves = kBlock / 64;
+  __shared__ int32_t s_c;
+  const int32_t n = B.counts[1];
+  for (int32_t c = next_chunk(B.queue + slot, s_c); c < n; c = next_chunk(B.queue + slot, s_c)) {
+    const JobDesc& J = B.jobs[B.pchunk_job[c]];
+    const int32_t base = (c - J.pchunk0) * kPixChunk;
+    const int32_t end = min(J.nH, base + kPixChunk);
+    unsigned long long my_abs = 0;
+    for (int32_t w = base + (int32_t)(threadIdx.x >> 6); w < end; w += kWaves) {
+      if (J.recon_mode == 1)
+        recon_pixel<1, false>(J.L, J.hlist, w, nullptr, nullptr, my_abs);
+      else
+        recon_pixel<0, false>(J.L, J.hlist, w, nullptr, nullptr, my_abs);
+    }
+    if ((threadIdx.x & 63) == 0 && my_abs) atomicAdd(J.absdiff, my_abs);
+  }
 }
 
 // ------------------------------------------------------------------------
@@ -1046,6 +1176,47 @@ hipError_t compact(hipStream_t st, const uint8_t* flags, int32_t n, int32_t* out
                    void* temp, size_t temp_bytes) {
   hipcub::CountingInputIterator<int32_t> it(0);
   return hipcub::DeviceSelect::Flagged(temp, temp_bytes, it, flags, out, d_count, n, st);
+}
+
+}  // namespace vi
+
+namespace vi {
+
+void launch_batch_zero(hipStream_t st, const BatchArgs& B, int32_t max_jobs) {
+  const int32_t n = max_jobs > kQueueSlots ? max_jobs : kQueueSlots;
+  kb_zero<<<dim3((unsigned)((n + 255) / 256)), 256, 0, st>>>(B);
+}
+
+void launch_batch_s0(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t slot) {
+  if (blk == 64)
+    kb_s0<64><<<grid, 64, 0, st>>>(B, slot);
+  else if (blk == 128)
+    kb_s0<128><<<grid, 128, 0, st>>>(B, slot);
+  else
+    kb_s0<256><<<grid, 256, 0, st>>>(B, slot);
+}
+
+void launch_batch_pass(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t s,
+                       int32_t k, int32_t parity, int32_t slot) {
+  if (blk == 64)
+    kb_pass<64><<<grid, 64, 0, st>>>(B, s, k, parity, slot);
+  else if (blk == 128)
+    kb_pass<128><<<grid, 128, 0, st>>>(B, s, k, parity, slot);
+  else
+    kb_pass<256><<<grid, 256, 0, st>>>(B, s, k, parity, slot);
+}
+
+void launch_batch_copy(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t slot) {
+  if (blk == 64)
+    kb_copy<64><<<grid, 64, 0, st>>>(B, slot);
+  else if (blk == 128)
+    kb_copy<128><<<grid, 128, 0, st>>>(B, slot);
+  else
+    kb_copy<256><<<grid, 256, 0, st>>>(B, slot);
+}
+
+void launch_batch_recon(hipStream_t st, const BatchArgs& B, int32_t grid, int32_t slot) {
+  kb_recon<<<grid, kBlock, 0, st>>>(B, slot);
 }
 
 }  // namespace vi

@@ -69,7 +69,20 @@ SIGNATURES = {
     "vi_reset_counters": (_i32, [_vp]),
     "vi_profile": (_i32, [_vp, _i32]),
     "vi_profile_read": (_i32, [_vp, _vp, _i32]),
+    "vi_output": (_i32, [_vp, _vp]),
+    "vi_done": (_i32, [_vp]),
+    "vi_batch_create": (_i32, [C.POINTER(_vp), _vp, _vp]),
+    "vi_batch_add": (_i32, [_vp, _vp]),
+    "vi_batch_remove": (_i32, [_vp, _vp]),
+    "vi_batch_step": (_i32, [_vp, C.POINTER(_i32)]),
+    "vi_batch_get_tune": (_i32, [_vp, _vp]),
+    "vi_batch_size": (_i32, [_vp]),
+    "vi_batch_destroy": (None, [_vp]),
 }
+
+
+class Tune(C.Structure):
+    _fields_ = [("block", C.c_int32), ("grid_mult", C.c_int32), ("tuned", C.c_int32)]
 
 
 class Counters(C.Structure):
@@ -163,6 +176,9 @@ class Clip:
         _check("vi_create", st)
         self.h = h
         self._abs = torch.zeros(1, dtype=torch.int64, device=self.device)
+        # set when the clip joins a batch: its work then runs on the batch's
+        # stream, so tensor results are synchronised before they are returned
+        self._foreign_stream = False
 
     def close(self):
         if getattr(self, "h", None):
@@ -198,11 +214,16 @@ class Clip:
     def _new(self, shape, dtype):
         return torch.empty(shape, dtype=dtype, device=self.device)
 
+    def _settle(self):
+        if self._foreign_stream:
+            torch.cuda.synchronize(self.device)
+
     def sets(self, level):
         W, H, T = self.dims(level)
         hole, dsrc, htil = (self._new((T, H, W), torch.uint8) for _ in range(3))
         _check("vi_level_sets", lib().vi_level_sets(self.h, level, _ptr(hole), _ptr(dsrc),
                                                     _ptr(htil)))
+        self._settle()
         return hole, dsrc, htil
 
     def get_state(self, level):
@@ -213,6 +234,7 @@ class Clip:
         nvox = self._new((T, H, W), torch.uint8)
         _check("vi_get_state", lib().vi_get_state(self.h, level, _ptr(rgbt), _ptr(cand),
                                                   _ptr(dist), _ptr(nvox)))
+        self._settle()
         return rgbt, cand, dist, nvox
 
     def set_state(self, level, rgbt=None, cand=None, dist=None, nvox=None):
@@ -234,6 +256,7 @@ class Clip:
         out = self._new((nH, 5), torch.float32) if want_out else None
         _check("vi_reconstruct", lib().vi_reconstruct(self.h, level, mode, _ptr(out),
                                                       _ptr(self._abs)))
+        self._settle()
         return out, self._abs
 
     def inpaint_level(self, level):
@@ -253,6 +276,15 @@ class Clip:
         if out is None:
             out = self._new((self.T, self.H, self.W, 3), torch.uint8)
         _check("vi_inpaint", lib().vi_inpaint(self.h, _ptr(out)))
+        return out
+
+    def done(self) -> bool:
+        return bool(lib().vi_done(self.h))
+
+    def output(self, out: torch.Tensor | None = None):
+        if out is None:
+            out = self._new((self.T, self.H, self.W, 3), torch.uint8)
+        _check("vi_output", lib().vi_output(self.h, _ptr(out)))
         return out
 
     def nominal_evals(self, level):
@@ -276,3 +308,62 @@ class Clip:
             _check("vi_profile_read", n)
         return [(KERNEL_KINDS[buf[i].kind], buf[i].level, int(buf[i].units), float(buf[i].ms))
                 for i in range(n)]
+
+
+class Batch:
+    """Clips that advance together, one EM iteration per step, each step one
+    captured graph launch over all members (vi_batch_*).
+
+    tune: None to autotune at the first step, or (block, grid_mult)."""
+
+    def __init__(self, tune=None, stream: torch.cuda.Stream | None = None):
+        h = C.c_void_p()
+        t = None
+        if tune is not None:
+            t = Tune(int(tune[0]), int(tune[1]), 1)
+        sh = C.c_void_p(stream.cuda_stream) if stream is not None else None
+        _check("vi_batch_create", lib().vi_batch_create(C.byref(h),
+                                                        C.byref(t) if t is not None else None, sh))
+        self.h = h
+        self.members = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vi_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, clip: "Clip"):
+        torch.cuda.synchronize(clip.device)  # inputs written on torch's stream
+        _check("vi_batch_add", lib().vi_batch_add(self.h, clip.h))
+        clip._foreign_stream = True
+        self.members.append(clip)
+
+    def remove(self, clip: "Clip"):
+        _check("vi_batch_remove", lib().vi_batch_remove(self.h, clip.h))
+        self.members.remove(clip)
+
+    def step(self) -> int:
+        n = C.c_int32(0)
+        _check("vi_batch_step", lib().vi_batch_step(self.h, C.byref(n)))
+        return int(n.value)
+
+    def tune(self):
+        t = Tune()
+        _check("vi_batch_get_tune", lib().vi_batch_get_tune(self.h, C.byref(t)))
+        return (t.block, t.grid_mult) if t.tuned else None
+
+    def __len__(self):
+        return int(lib().vi_batch_size(self.h))
+
+    def run(self, max_steps: int = 100000) -> int:
+        """Steps until every member has finished; returns the step count."""
+        for k in range(max_steps):
+            if self.step() == len(self.members):
+                return k + 1
+        raise RuntimeError("batch did not finish")

@@ -1,0 +1,120 @@
+"""Batched execution (vi_batch_*): many clips of uneven sizes, masks and
+pyramid depths advance together, one captured graph launch of persistent
+kernels per EM iteration.  Every member's result must be bit-identical to
+the same clip inpainted alone, for any tile shape the autotuner may pick,
+and when clips join a running batch."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1503_05528_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vi():
+    from paper_1503_05528_amd import vi as _vi
+    _vi.lib()
+    return _vi
+
+
+def clips():
+    return [
+        (synth.small(31, 61, 47, 11, levels=2, frac=0.05), dict(levels=2, seed=5)),
+        (synth.small(32, 83, 66, 9, levels=3, frac=0.04, kind="box"), dict(levels=3, seed=6)),
+        (synth.tiny(), dict(levels=1, seed=7)),
+        (synth.small(33, 50, 40, 12, levels=2, frac=0.02), dict(levels=2, seed=8, recon_mode=1)),
+        (synth.small(34, 96, 72, 10, levels=3, frac=0.07), dict(levels=3, seed=9, em_tol=-1.0,
+                                                               em_max_iters=4)),
+    ]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def alone(vi, clip, kw):
+    g = vi.Clip(dev(clip.occluded_input()), dev(clip.mask), **kw)
+    out = g.inpaint().cpu().numpy()
+    g.close()
+    return out
+
+
+@pytest.fixture(scope="module")
+def references(vi):
+    return [alone(vi, c, kw) for c, kw in clips()]
+
+
+@pytest.mark.parametrize("tune", [None, (64, 2), (128, 1), (256, 8)])
+def test_batch_matches_alone(vi, references, tune):
+    print(f"[case] batch tune={tune}", flush=True)
+    b = vi.Batch(tune=tune)
+    members = []
+    for c, kw in clips():
+        g = vi.Clip(dev(c.occluded_input()), dev(c.mask), **kw)
+        b.add(g)
+        members.append(g)
+    steps = b.run()
+    assert steps > 1
+    if tune is None:
+        assert b.tune() is not None
+    for g, ref in zip(members, references):
+        assert g.done()
+        assert np.array_equal(g.output().cpu().numpy(), ref)
+
+
+def test_clips_joining_a_running_batch(vi, references):
+    cs = clips()
+    b = vi.Batch(tune=(128, 4))
+    members = {}
+    for i in (0, 1):
+        c, kw = cs[i]
+        members[i] = vi.Clip(dev(c.occluded_input()), dev(c.mask), **kw)
+        b.add(members[i])
+    b.step()
+    b.step()
+    for i in (2, 3, 4):
+        c, kw = cs[i]
+        members[i] = vi.Clip(dev(c.occluded_input()), dev(c.mask), **kw)
+        b.add(members[i])
+        b.step()
+    b.run()
+    for i, g in members.items():
+        assert np.array_equal(g.output().cpu().numpy(), references[i]), i
+
+
+def test_batch_counters_match_alone(vi):
+    c, kw = clips()[1]
+    g1 = vi.Clip(dev(c.occluded_input()), dev(c.mask), **kw)
+    g1.inpaint()
+    b = vi.Batch(tune=(256, 4))
+    g2 = vi.Clip(dev(c.occluded_input()), dev(c.mask), **kw)
+    b.add(g2)
+    b.run()
+    a, bb = g1.counters(), g2.counters()
+    for k in ("nominal_evals", "effective_evals", "searches", "em_iters", "recon_pixels"):
+        assert a[k] == bb[k], k
+
+
+def test_batch_errors(vi):
+    c, kw = clips()[0]
+    b = vi.Batch(tune=(128, 2))
+    g = vi.Clip(dev(c.occluded_input()), dev(c.mask), **kw)
+    b.add(g)
+    with pytest.raises(vi.ViError):
+        b.add(g)
+    other = vi.Clip(dev(c.occluded_input()), dev(c.mask), levels=2, pm_iters=4)
+    with pytest.raises(vi.ViError) as e:
+        b.add(other)
+    assert e.value.status == -1
+    nojf = vi.Clip(dev(c.occluded_input()), dev(c.mask), levels=2, jf_steps=[])
+    with pytest.raises(vi.ViError):
+        vi.Batch().add(nojf)
+    with pytest.raises(vi.ViError):
+        vi.Batch(tune=(96, 2))
+    with pytest.raises(vi.ViError) as e:
+        other.output()
+    assert e.value.status == -4
+    b.remove(g)
+    assert len(b) == 0
