@@ -45,7 +45,41 @@ def parse():
     ap.add_argument("--batch-clips", type=int, default=64)
     ap.add_argument("--served-seconds", type=float, default=30.0)
     ap.add_argument("--served-rate", type=float, default=4.0)
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="summarise a rocprofv3 --output-format csv directory and exit")
     return ap.parse_args()
+
+
+KERNEL_SRC = os.path.join(ROOT, "paper_1503_05528_amd", "csrc", "vi_kernels.hip")
+COUNTERS_JSON = os.path.join(ROOT, "profiles", "k_pass_sd_hbm_counters.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+
+
+def summarize_counters(d):
+    """Per kernel and grid size: dispatches, mean duration and mean value of
+    every counter of a rocprofv3 CSV output directory."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        rows += list(csv.DictReader(open(f)))
+    agg = {}
+    for r in rows:
+        k = (r["Kernel_Name"].split("(")[0].replace("void ", ""), int(r["Grid_Size"]))
+        a = agg.setdefault(k, {"dispatch": {}, "counters": {}})
+        a["dispatch"][r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        a["counters"].setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    out = []
+    for (name, grid), a in sorted(agg.items()):
+        ds = list(a["dispatch"].values())
+        out.append({"kernel": name, "grid": grid, "dispatches": len(ds),
+                    "mean_us": sum(ds) / len(ds) / 1000.0,
+                    "counters": {c: sum(v) / len(v) for c, v in sorted(a["counters"].items())}})
+    return out
 
 
 def _gen_batch_clip(seed):
@@ -220,6 +254,9 @@ def cpu_baseline(clip, levels, em_iters, level):
 
 def main():
     a = parse()
+    if a.summarize_counters:
+        print(json.dumps(summarize_counters(a.summarize_counters), indent=1))
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
               "(the per-clip path and its batching are single-GPU)", file=sys.stderr)
@@ -260,7 +297,7 @@ def main():
     torch.cuda.synchronize()
     lat = []
     recs = []
-    nominal = effective = 0
+    nominal = effective = pass_evals = 0
     t0 = time.perf_counter()
     for _ in range(a.steps):
         s0 = time.perf_counter()
@@ -269,6 +306,7 @@ def main():
         recs += rec
         nominal += cnt["nominal_evals"]
         effective += cnt["effective_evals"]
+        pass_evals += cnt["pass_evals"]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1000.0 * elapsed / a.steps
@@ -285,14 +323,27 @@ def main():
         by_level[key] = round(by_level.get(key, 0.0) + ms / a.steps, 3)
     pas = kinds.get("pass", {"launches": 1, "units": 0, "ms": 1.0})
     avg_ms = pas["ms"] / pas["launches"]
-    bytes_per_launch = BYTES_PER_EVAL * pas["units"] / pas["launches"]
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    # algorithmic bytes: one candidate patch (125 voxels x 5 bytes) per
+    # distance the pass launches compute
+    evals_per_launch = pass_evals / pas["launches"]
+    achieved = BYTES_PER_EVAL * evals_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    hbm_gbs = None
+    if os.path.exists(COUNTERS_JSON):
+        cj = json.load(open(COUNTERS_JSON))
+        if cj.get("source_sha256") == kernel_source_hash() and cj.get("workload") == a.config:
+            traffic = cj["hbm_bytes_per_launch"]
+            hbm_gbs = traffic / (cj["mean_launch_us"] * 1e-6) / 1e9
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-        "kernel": "k_pass (propagation + fused random search)",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "kernel": "k_pass<false> (propagation pass with fused random search)",
         "avg_launch_ms": round(avg_ms, 5), "launches": pas["launches"],
-        "evals_per_launch": round(pas["units"] / pas["launches"], 1),
+        "evals_per_launch": round(evals_per_launch, 1),
+        "nominal_evals_per_launch": round(pas["units"] / pas["launches"], 1),
+        "nominal_gather_gbs": round(BYTES_PER_EVAL * pas["units"] / pas["launches"]
+                                    / (avg_ms * 1e-3) / 1e9, 1),
+        "measured_hbm_gbs": None if hbm_gbs is None else round(hbm_gbs, 1),
     }
     line = {
         "metric": "NNF patch-distance evals/s (nominal)",

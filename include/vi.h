@@ -120,7 +120,7 @@ vi_status vi_reconstruct(vi_ctx* ctx, int32_t level, int32_t mode, float* out_f,
 vi_status vi_inpaint_level(vi_ctx* ctx, int32_t level, int32_t* em_iters_run);
 
 /* Onion-peel initialisation of the coarsest level (Sec. 3.5, Alg. 3, Eqs.
- * (3.9)-(3.10)).  layers_run (host) or NULL.  Syncs once per layer. */
+ * (3.9)-(3.11)).  layers_run (host) or NULL.  Syncs once per layer. */
 vi_status vi_onion_init(vi_ctx* ctx, int32_t* layers_run);
 
 /* Level transition level+1 -> level (Sec. 3.6): nearest-neighbour upsampling
@@ -217,6 +217,9 @@ typedef struct {
   int64_t searches;        /* searches run (EM iterations and onion layers) */
   int64_t em_iters;        /* EM iterations run (all levels) */
   int64_t recon_pixels;    /* hole pixels reconstructed (all reconstructions) */
+  int64_t pass_evals;      /* of effective_evals: propagation and random-search passes */
+  int64_t init_evals;      /* of effective_evals: step 0 of the EM-loop searches */
+  int64_t onion_evals;     /* of effective_evals: onion-peel searches */
 } vi_counters;
 vi_status vi_get_counters(vi_ctx* ctx, vi_counters* out);
 vi_status vi_reset_counters(vi_ctx* ctx);

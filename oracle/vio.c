@@ -742,8 +742,8 @@ int vio_inpaint_level(vio_ctx* ctx, int32_t level, int32_t* iters_run) {
 /* hole; each layer is H' minus its erosion by the 3x3x3 cube (voxels       */
 /* outside the volume count as occluded).  The layer's targets are the      */
 /* voxels outside H' whose patch touches the layer; they are matched with   */
-/* the partial distance over voxels outside H' (Eq. (3.9)), and the layer   */
-/* is reconstructed from those targets only (Eq. (3.10)).                   */
+/* the partial distance over voxels outside H' (Eq. (3.10)), and the layer  */
+/* is reconstructed from those targets only (Eq. (3.11)).                   */
 /* ------------------------------------------------------------------------ */
 int vio_onion_init(vio_ctx* ctx, int32_t* layers_run) {
   if (!ctx) return VIO_E_INVAL;

@@ -60,7 +60,8 @@ struct vi_ctx {
   void* ctemp = nullptr;  // compaction scratch
   size_t ctemp_bytes = 0;
   int32_t* d_count = nullptr;             // [2]
-  unsigned long long* d_u64 = nullptr;    // [0] absdiff, [1..2] set_state checks, [3] evals
+  unsigned long long* d_u64 = nullptr;    // [0] absdiff, [1..2] set_state checks,
+                                          // [3..5] evaluations: passes, step 0, onion
   // onion-peel scratch (coarsest level)
   uint8_t *o_Hp = nullptr, *o_E = nullptr, *o_bd = nullptr, *o_S = nullptr;
   uint8_t *o_t1 = nullptr, *o_t2 = nullptr;
@@ -239,11 +240,15 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
   A.smask = smask;
   A.excl = excl;
   A.step = step;
-  A.evals = c->d_u64 + 3;
+  // onion searches (masked) count apart from the EM loop's
+  unsigned long long* ev_pass = c->d_u64 + (excl ? 5 : 3);
+  unsigned long long* ev_init = c->d_u64 + (excl ? 5 : 4);
+  A.evals = ev_init;
   A.nin = d.nnf0;
   A.nout = d.nnf0;
   int r = prof_begin(c);
   vi::launch_s0(c->st, d, A);
+  A.evals = ev_pass;
   prof_end(c, r, VI_K_INIT, level, nS);
   VI_TRY(launched("s0"));
   int2* buf[2] = {d.nnf0, d.nnf1};
@@ -651,21 +656,24 @@ int64_t vi_nominal_evals(const vi_ctx* c, int32_t level) {
 
 vi_status vi_get_counters(vi_ctx* c, vi_counters* out) {
   if (!c || !out) return fail(VI_E_INVAL, "null argument");
-  unsigned long long v = 0;
-  VI_HIP(hipMemcpyAsync(&v, c->d_u64 + 3, sizeof(v), hipMemcpyDeviceToHost, c->st));
+  unsigned long long v[3] = {0, 0, 0};
+  VI_HIP(hipMemcpyAsync(v, c->d_u64 + 3, sizeof(v), hipMemcpyDeviceToHost, c->st));
   VI_TRY(sync(c));
   out->nominal_evals = c->n_nominal;
-  out->effective_evals = (int64_t)v;
+  out->effective_evals = (int64_t)(v[0] + v[1] + v[2]);
   out->searches = c->n_searches;
   out->em_iters = c->n_em;
   out->recon_pixels = c->n_recon;
+  out->pass_evals = (int64_t)v[0];
+  out->init_evals = (int64_t)v[1];
+  out->onion_evals = (int64_t)v[2];
   return VI_OK;
 }
 
 vi_status vi_reset_counters(vi_ctx* c) {
   if (!c) return fail(VI_E_INVAL, "null context");
   c->n_nominal = c->n_searches = c->n_em = c->n_recon = 0;
-  vi::launch_fill_u64(c->st, c->d_u64 + 3, 1);
+  vi::launch_fill_u64(c->st, c->d_u64 + 3, 3);
   return launched("fill");
 }
 
@@ -812,6 +820,7 @@ vi_status batch_build(vi_batch* b, int blk, bool scratch_evals) {
     J.step = (uint64_t)c->em_k;
     J.absdiff = b->d_abs + b->h_jobs.size();
     J.evals = scratch_evals ? b->d_scratch : c->d_u64 + 3;
+    J.evals_init = scratch_evals ? b->d_scratch : c->d_u64 + 4;
     const int32_t rmax = r_max(lv.d);
     for (int k = 0; k <= vi::kMaxPmIters; ++k) J.R[k] = k == 0 ? 0 : rs_radius(c->prm, rmax, k);
     J.tchunk0 = (int32_t)b->h_tj.size();

@@ -83,7 +83,8 @@ struct JobDesc {
   int32_t pad_;
   uint64_t step;    // EM index at the level (Philox counter word 1)
   unsigned long long* absdiff;
-  unsigned long long* evals;
+  unsigned long long* evals;       // distances computed by the passes
+  unsigned long long* evals_init;  // distances computed by step 0
   int32_t R[kMaxPmIters + 1];  // random-search radius of iteration k
 };
 

@@ -1,7 +1,7 @@
 // vi_kernels.hip -- gfx950 kernels of the inpainting hot path.
 //
 // Paper anchors (Newson et al., "Video Inpainting of Complex Scenes"):
-//   patch distance           Sec. 2 Eq. (2.2), Sec. 3.3, Sec. 3.5 Eq. (3.9)
+//   patch distance           Sec. 2 Eq. (2.2), Sec. 3.3 Eq. (3.6), Sec. 3.5 Eq. (3.10)
 //   ANN search               Sec. 3.1, Alg. 1, Eq. (3.1)
 //   reconstruction           Sec. 3.2 Eqs. (3.2)-(3.4), Sec. 3.3 Eq. (3.8)
 //   pyramids and features    Sec. 3.3 Eqs. (3.5), (3.7), Sec. 3.6, Alg. 4
@@ -723,7 +723,7 @@ __global__ __launch_bounds__(BLK) void kb_s0(BatchArgs B, int32_t slot) {
     A.nin = J.L.nnf0;
     A.step = J.step;
     const int ne = s0_target<false>(J.L, A, (c - J.tchunk0) * BLK + (int32_t)threadIdx.x);
-    count_evals(J.evals, ne);
+    count_evals(J.evals_init, ne);
   }
 }
 

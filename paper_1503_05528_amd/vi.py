@@ -87,7 +87,9 @@ class Tune(C.Structure):
 
 class Counters(C.Structure):
     _fields_ = [("nominal_evals", C.c_int64), ("effective_evals", C.c_int64),
-                ("searches", C.c_int64), ("em_iters", C.c_int64), ("recon_pixels", C.c_int64)]
+                ("searches", C.c_int64), ("em_iters", C.c_int64), ("recon_pixels", C.c_int64),
+                ("pass_evals", C.c_int64), ("init_evals", C.c_int64),
+                ("onion_evals", C.c_int64)]
 
 
 class KernelTime(C.Structure):
