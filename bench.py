@@ -54,6 +54,11 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1503_05528_amd", "csrc", "vi_kernels.hip"
 COUNTERS_JSON = os.path.join(ROOT, "profiles", "k_pass_sd_hbm_counters.json")
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result line goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash():
     import hashlib
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
@@ -92,7 +97,7 @@ def gen_batch_clips(n, base_seed=1000):
     """The mixed-size batch workload, generated in worker processes."""
     import multiprocessing as mp
     ctx = mp.get_context("spawn")
-    with ctx.Pool(min(16, max(1, os.cpu_count() or 1))) as pool:
+    with ctx.Pool(min(8, max(1, os.cpu_count() or 1))) as pool:
         return pool.map(_gen_batch_clip, [base_seed + i for i in range(n)])
 
 
@@ -112,6 +117,7 @@ def batched_vs_serial(clips, em_iters):
     torch.cuda.synchronize()
     serial_out, service = [], []
     nominal = 0
+    log(f"batched: {len(dev)} clips one at a time")
     t0 = time.perf_counter()
     for i, (v, m, L) in enumerate(dev):
         s0 = time.perf_counter()
@@ -122,6 +128,7 @@ def batched_vs_serial(clips, em_iters):
         service.append(time.perf_counter() - s0)
     torch.cuda.synchronize()
     t_serial = time.perf_counter() - t0
+    log("batched: tuning on a throw-away batch")
     b = vi.Batch()
     # tune once on a throw-away batch of the same clips so the timed run
     # measures steady-state steps
@@ -134,6 +141,7 @@ def batched_vs_serial(clips, em_iters):
         g.close()
     b.close()
     torch.cuda.synchronize()
+    log(f"batched: all clips in one batch, tune {tune}")
     t0 = time.perf_counter()
     b = vi.Batch(tune=tune)
     members = [vi.Clip(v, m, params=mk(i)) for i, (v, m, L) in enumerate(dev)]
@@ -292,6 +300,7 @@ def main():
         g.close()
         return out, rec, cnt
 
+    log(f"{a.config}: {a.warmup} warm-up and {a.steps} timed steps")
     for _ in range(a.warmup):
         one_step()
     torch.cuda.synchronize()
@@ -377,12 +386,14 @@ def main():
         if not a.no_batched:
             line["batched"] = bres
         if not a.no_served:
+            log(f"served: {a.served_seconds} s Poisson trace")
             # service time of the SD clip alone = this run's SD step latency
             svc = {i: service[i] for i in range(len(bclips))}
             svc[-1] = statistics.median(lat)
             line["served"] = served(bclips, (clip.occluded_input(), clip.mask, levels),
                                     a.served_seconds, a.served_rate, a.em_iters, svc)
     if not a.no_cpu_baseline:
+        log("cpu baseline: oracle search")
         line["cpu_baseline"] = cpu_baseline(clip, levels, a.em_iters, a.cpu_level)
     print(json.dumps(line), flush=True)
 

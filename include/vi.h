@@ -178,16 +178,20 @@ int32_t vi_done(const vi_ctx* ctx);
 /* ---------------------------------------------------------------------------
  * Batches.  Many clips of uneven sizes and masks advance together: every
  * vi_batch_step runs one EM iteration (search + reconstruction, Alg. 4 inner
- * loop) of every member in the EM phase as ONE captured HIP graph of
- * persistent kernels over all members' targets and hole pixels; onion peels,
+ * loop) of every member in the EM phase as one set of launches over all
+ * members' targets and hole pixels — a captured HIP graph of persistent
+ * kernels, or direct launches sized to the step (vi_tune); the onion peels
+ * of members that start together run layer by layer as batched launches;
  * level transitions and final reconstructions of individual members run
- * between the graph launches.  Each member's result is bit-identical to
+ * between steps.  Each member's result is bit-identical to
  * vi_inpaint on that clip alone.  Members must share pm_iters and jf_steps
  * (n_jf >= 1).
  * ------------------------------------------------------------------------- */
 typedef struct {
   int32_t block;     /* targets per workgroup: 64, 128 or 256 */
-  int32_t grid_mult; /* persistent grid = compute units x grid_mult */
+  int32_t grid_mult; /* 1..64: persistent kernels, grid = compute units x grid_mult,
+                        one captured graph per step; 0: one workgroup per chunk,
+                        launched directly with grids sized to the step */
   int32_t tuned;     /* nonzero: use these values; zero: autotune at the first step */
 } vi_tune;
 typedef struct vi_batch vi_batch;
@@ -202,7 +206,9 @@ vi_status vi_batch_create(vi_batch** out, const vi_tune* tune, void* hip_stream)
 vi_status vi_batch_add(vi_batch* b, vi_ctx* ctx);
 vi_status vi_batch_remove(vi_batch* b, vi_ctx* ctx);
 /* One step of every member; n_done (host) receives the number of members
- * that have finished.  Syncs. */
+ * whose work has all been enqueued (their results are final once the stream
+ * reaches this point; vi_output syncs).  Syncs once per step when some member
+ * uses the stopping test (em_tol >= 0); otherwise only enqueues. */
 vi_status vi_batch_step(vi_batch* b, int32_t* n_done);
 vi_status vi_batch_get_tune(const vi_batch* b, vi_tune* out);
 int32_t vi_batch_size(const vi_batch* b);

@@ -6,6 +6,7 @@
 // EM loop with its stopping test, level transitions, final reconstruction).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -322,10 +323,9 @@ vi_status inpaint_level(vi_ctx* c, int32_t level, int32_t* iters) {
   return VI_OK;
 }
 
-vi_status onion(vi_ctx* c, int32_t* layers_run) {
-  const int32_t level = c->L - 1;
-  Level& lv = c->lv[level];
-  const vi::DevLevel& d = lv.d;
+// scratch of the onion peel, empty shift maps, H' = the coarsest hole
+vi_status onion_prepare(vi_ctx* c) {
+  const vi::DevLevel& d = c->lv[c->L - 1].d;
   const size_t V = (size_t)d.V;
   if (!c->o_Hp) {
     VI_TRY(dalloc(c, &c->o_Hp, V));
@@ -340,6 +340,14 @@ vi_status onion(vi_ctx* c, int32_t* layers_run) {
   vi::launch_fill_nnf(c->st, d.nnf0, d.nvox, d.V);
   vi::launch_fill_nnf(c->st, d.nnf1, nullptr, d.V);
   VI_HIP(hipMemcpyAsync(c->o_Hp, d.hole, V, hipMemcpyDeviceToDevice, c->st));
+  return launched("onion set-up");
+}
+
+vi_status onion(vi_ctx* c, int32_t* layers_run) {
+  const int32_t level = c->L - 1;
+  Level& lv = c->lv[level];
+  const vi::DevLevel& d = lv.d;
+  VI_TRY(onion_prepare(c));
   uint8_t* Hp = c->o_Hp;
   uint8_t* E = c->o_E;
   int32_t layer = 0;
@@ -711,17 +719,9 @@ int32_t vi_profile_read(vi_ctx* c, vi_kernel_time* out, int32_t cap) {
 // ===========================================================================
 namespace {
 
-// Alg. 4 driven step by step: start = onion peel of the coarsest level;
-// after the EM loop of a level stops, transition to the next finer level or,
-// at level 0, the final best-patch reconstruction.
-vi_status drive_start(vi_ctx* c) {
-  VI_TRY(onion(c, nullptr));
-  c->phase = 1;
-  c->cur_level = c->L - 1;
-  c->em_k = 0;
-  return VI_OK;
-}
-
+// Alg. 4 driven step by step: after the EM loop of a level stops, transition
+// to the next finer level or, at level 0, the final best-patch
+// reconstruction.
 vi_status drive_finish_level(vi_ctx* c) {
   c->lv[c->cur_level].complete = true;
   if (c->cur_level > 0) {
@@ -774,7 +774,15 @@ struct vi_batch {
   std::vector<vi::JobDesc> h_jobs;
   std::vector<int32_t> h_tj, h_pj;
   std::vector<vi_ctx*> job_ctx;
-  std::vector<unsigned long long> h_abs;
+  // pinned staging of the uploads, double-buffered: the host fills one
+  // while the copy from the other may still be in flight
+  struct Stage {
+    void* host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+  } stage[2];
+  int stage_next = 0;
+  unsigned long long* h_abs = nullptr;  // pinned, cap_jobs
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t steps_run = 0;
@@ -791,67 +799,100 @@ void batch_free(vi_batch* b) {
                   (void*)b->d_counts, (void*)b->d_abs, (void*)b->d_scratch, (void*)b->d_queue})
     if (p) (void)hipFree(p);
   b->d_queue = nullptr;
+  for (auto& st : b->stage) {
+    if (st.done) (void)hipEventDestroy(st.done);
+    if (st.host) (void)hipHostFree(st.host);
+    st.done = nullptr;
+    st.host = nullptr;
+  }
+  if (b->h_abs) (void)hipHostFree(b->h_abs);
+  b->h_abs = nullptr;
   b->d_jobs = nullptr;
   b->d_tchunk_job = b->d_pchunk_job = b->d_counts = nullptr;
   b->d_abs = b->d_scratch = nullptr;
 }
 
-vi_status batch_bail(vi_batch* b, vi_status s) {
-  batch_free(b);
-  return s;
-}
 
-// job table and chunk maps of the members in the EM phase, for a block size
-vi_status batch_build(vi_batch* b, int blk, bool scratch_evals) {
-  b->h_jobs.clear();
+// uploads a job table and its chunk maps (chunks of `blk` targets and of
+// kPixChunk hole pixels per job)
+vi_status batch_upload(vi_batch* b, int blk) {
   b->h_tj.clear();
   b->h_pj.clear();
-  b->job_ctx.clear();
-  for (vi_ctx* c : b->members) {
-    if (c->phase != 1) continue;
-    const Level& lv = c->lv[c->cur_level];
-    vi::JobDesc J{};
-    J.L = lv.d;
-    J.tlist = lv.tlist;
-    J.hlist = lv.hlist;
-    J.nS = lv.nS;
-    J.nH = lv.nH;
-    J.recon_mode = c->prm.recon_mode;
-    J.step = (uint64_t)c->em_k;
-    J.absdiff = b->d_abs + b->h_jobs.size();
-    J.evals = scratch_evals ? b->d_scratch : c->d_u64 + 3;
-    J.evals_init = scratch_evals ? b->d_scratch : c->d_u64 + 4;
-    const int32_t rmax = r_max(lv.d);
-    for (int k = 0; k <= vi::kMaxPmIters; ++k) J.R[k] = k == 0 ? 0 : rs_radius(c->prm, rmax, k);
+  for (size_t j = 0; j < b->h_jobs.size(); ++j) {
+    vi::JobDesc& J = b->h_jobs[j];
     J.tchunk0 = (int32_t)b->h_tj.size();
     J.pchunk0 = (int32_t)b->h_pj.size();
-    const int32_t nt = (lv.nS + blk - 1) / blk;
-    const int32_t np = (lv.nH + vi::kPixChunk - 1) / vi::kPixChunk;
-    const int32_t j = (int32_t)b->h_jobs.size();
-    for (int32_t i = 0; i < nt; ++i) b->h_tj.push_back(j);
-    for (int32_t i = 0; i < np; ++i) b->h_pj.push_back(j);
-    b->h_jobs.push_back(J);
-    b->job_ctx.push_back(c);
+    const int32_t nt = (J.nS + blk - 1) / blk;
+    const int32_t np = (J.nH + vi::kPixChunk - 1) / vi::kPixChunk;
+    for (int32_t i = 0; i < nt; ++i) b->h_tj.push_back((int32_t)j);
+    for (int32_t i = 0; i < np; ++i) b->h_pj.push_back((int32_t)j);
   }
   if ((int32_t)b->h_jobs.size() > b->cap_jobs)
     return fail(VI_E_BUDGET, "more clips in the EM phase than the batch holds");
   if ((int32_t)b->h_tj.size() > b->cap_tchunks || (int32_t)b->h_pj.size() > b->cap_pchunks)
     return fail(VI_E_BUDGET, "the batch's work lists are full");
-  const int32_t counts[3] = {(int32_t)b->h_tj.size(), (int32_t)b->h_pj.size(),
-                             (int32_t)b->h_jobs.size()};
-  if (!b->h_jobs.empty())
-    VI_HIP(hipMemcpyAsync(b->d_jobs, b->h_jobs.data(), sizeof(vi::JobDesc) * b->h_jobs.size(),
+  const int32_t counts[4] = {(int32_t)b->h_tj.size(), (int32_t)b->h_pj.size(),
+                             (int32_t)b->h_jobs.size(), 0};
+  const size_t bj = sizeof(vi::JobDesc) * b->h_jobs.size();
+  const size_t bt = sizeof(int32_t) * b->h_tj.size();
+  const size_t bp = sizeof(int32_t) * b->h_pj.size();
+  const size_t need = sizeof(counts) + bj + bt + bp;
+  vi_batch::Stage& sg = b->stage[b->stage_next];
+  b->stage_next ^= 1;
+  if (sg.done) VI_HIP(hipEventSynchronize(sg.done));  // its previous copies are done
+  if (sg.bytes < need) {
+    if (sg.host) VI_HIP(hipHostFree(sg.host));
+    sg.host = nullptr;
+    sg.bytes = 0;
+    VI_HIP(hipHostMalloc(&sg.host, need * 2, hipHostMallocDefault));
+    sg.bytes = need * 2;
+  }
+  if (!sg.done) VI_HIP(hipEventCreateWithFlags(&sg.done, hipEventDisableTiming));
+  char* h = static_cast<char*>(sg.host);
+  std::memcpy(h, counts, sizeof(counts));
+  std::memcpy(h + sizeof(counts), b->h_jobs.data(), bj);
+  std::memcpy(h + sizeof(counts) + bj, b->h_tj.data(), bt);
+  std::memcpy(h + sizeof(counts) + bj + bt, b->h_pj.data(), bp);
+  VI_HIP(hipMemcpyAsync(b->d_counts, h, sizeof(counts), hipMemcpyHostToDevice, b->st));
+  if (bj) VI_HIP(hipMemcpyAsync(b->d_jobs, h + sizeof(counts), bj, hipMemcpyHostToDevice, b->st));
+  if (bt)
+    VI_HIP(hipMemcpyAsync(b->d_tchunk_job, h + sizeof(counts) + bj, bt, hipMemcpyHostToDevice,
+                          b->st));
+  if (bp)
+    VI_HIP(hipMemcpyAsync(b->d_pchunk_job, h + sizeof(counts) + bj + bt, bp,
                           hipMemcpyHostToDevice, b->st));
-  if (!b->h_tj.empty())
-    VI_HIP(hipMemcpyAsync(b->d_tchunk_job, b->h_tj.data(), sizeof(int32_t) * b->h_tj.size(),
-                          hipMemcpyHostToDevice, b->st));
-  if (!b->h_pj.empty())
-    VI_HIP(hipMemcpyAsync(b->d_pchunk_job, b->h_pj.data(), sizeof(int32_t) * b->h_pj.size(),
-                          hipMemcpyHostToDevice, b->st));
-  VI_HIP(hipMemcpyAsync(b->d_counts, counts, sizeof(counts), hipMemcpyHostToDevice, b->st));
-  // pageable sources: complete the copies before the host vectors change
-  VI_HIP(hipStreamSynchronize(b->st));
+  VI_HIP(hipEventRecord(sg.done, b->st));
   return VI_OK;
+}
+
+vi::JobDesc job_for(vi_batch* b, vi_ctx* c, int32_t level, size_t slot, bool scratch_evals) {
+  const Level& lv = c->lv[level];
+  vi::JobDesc J{};
+  J.L = lv.d;
+  J.tlist = lv.tlist;
+  J.hlist = lv.hlist;
+  J.nS = lv.nS;
+  J.nH = lv.nH;
+  J.recon_mode = c->prm.recon_mode;
+  J.step = (uint64_t)c->em_k;
+  J.absdiff = b->d_abs + slot;
+  J.evals = scratch_evals ? b->d_scratch : c->d_u64 + 3;
+  J.evals_init = scratch_evals ? b->d_scratch : c->d_u64 + 4;
+  const int32_t rmax = r_max(lv.d);
+  for (int k = 0; k <= vi::kMaxPmIters; ++k) J.R[k] = k == 0 ? 0 : rs_radius(c->prm, rmax, k);
+  return J;
+}
+
+// job table of the members in the EM phase, for a block size
+vi_status batch_build(vi_batch* b, int blk, bool scratch_evals) {
+  b->h_jobs.clear();
+  b->job_ctx.clear();
+  for (vi_ctx* c : b->members) {
+    if (c->phase != 1) continue;
+    b->h_jobs.push_back(job_for(b, c, c->cur_level, b->h_jobs.size(), scratch_evals));
+    b->job_ctx.push_back(c);
+  }
+  return batch_upload(b, blk);
 }
 
 vi::BatchArgs batch_args(const vi_batch* b) {
@@ -861,28 +902,109 @@ vi::BatchArgs batch_args(const vi_batch* b) {
   B.pchunk_job = b->d_pchunk_job;
   B.counts = b->d_counts;
   B.queue = b->d_queue;
+  B.direct = b->grid_mult == 0 ? 1 : 0;
   return B;
 }
 
 // the launches of one batched EM iteration: step 0, every propagation pass
 // with the random search fused into the last pass of each iteration, the copy
 // back when the pass count is odd, and the reconstruction
-vi_status batch_enqueue_iteration(vi_batch* b) {
+// grid_mult == 0 selects direct launches, sized to this step's chunk counts
+// (not captured in a graph); otherwise persistent launches of a fixed grid.
+vi_status batch_enqueue_iteration(vi_batch* b, bool masked = false) {
   const vi::BatchArgs B = batch_args(b);
-  const int32_t grid = b->ncu * b->grid_mult;
+  const int32_t nt = (int32_t)b->h_tj.size(), np = (int32_t)b->h_pj.size();
+  const int32_t grid = B.direct ? (nt > 0 ? nt : 1) : b->ncu * b->grid_mult;
+  const int32_t rgrid = B.direct ? (np > 0 ? np : 1) : b->ncu * 8;
   int32_t slot = 0;
   vi::launch_batch_zero(b->st, B, b->cap_jobs);
-  vi::launch_batch_s0(b->st, B, b->blk, grid, slot++);
+  vi::launch_batch_s0(b->st, B, b->blk, grid, slot++, masked);
   int parity = 0;
   for (int k = 1; k <= b->sched.pm_iters; ++k)
     for (int js = 0; js < b->sched.n_jf; ++js) {
       vi::launch_batch_pass(b->st, B, b->blk, grid, b->sched.jf_steps[js],
-                            js == b->sched.n_jf - 1 ? k : 0, parity, slot++);
+                            js == b->sched.n_jf - 1 ? k : 0, parity, slot++, masked);
       parity ^= 1;
     }
   if (parity) vi::launch_batch_copy(b->st, B, b->blk, grid, slot++);
-  vi::launch_batch_recon(b->st, B, b->ncu * 8, slot++);
+  vi::launch_batch_recon(b->st, B, rgrid, slot++, masked);
   return launched("batched iteration");
+}
+
+// Onion peels (Sec. 3.5, Alg. 3) of clips that start together: layer k of
+// every clip is peeled at once.  Each clip's masks and target lists are built
+// on the batch's stream, the layer sizes of all clips come back with one
+// synchronisation, and the layer's masked searches and reconstructions run as
+// one set of batched launches.  Per clip the sequence of operations and the
+// random numbers (step 2^32 + layer) are those of vi_onion_init.
+vi_status batch_onion(vi_batch* b, std::vector<vi_ctx*> active) {
+  // before tuning, the onion runs direct launches of 256-target workgroups
+  const int blk = b->blk > 0 ? b->blk : 256;
+  const int saved_blk = b->blk, saved_mult = b->grid_mult;
+  b->blk = blk;
+  if (!b->tuned) b->grid_mult = 0;
+  for (vi_ctx* c : active) VI_TRY(onion_prepare(c));
+  std::vector<uint8_t*> Hp(active.size()), E(active.size());
+  for (size_t i = 0; i < active.size(); ++i) {
+    Hp[i] = active[i]->o_Hp;
+    E[i] = active[i]->o_E;
+  }
+  std::vector<int32_t> cnt(2 * active.size());
+  for (int32_t layer = 0; !active.empty(); ++layer) {
+    for (size_t i = 0; i < active.size(); ++i) {
+      vi_ctx* c = active[i];
+      const vi::DevLevel& d = c->lv[c->L - 1].d;
+      vi::launch_erode3(b->st, Hp[i], E[i], c->o_bd, d.W, d.H, d.T);
+      vi::launch_dilate5(b->st, c->o_bd, c->o_S, c->o_t1, c->o_t2, d.W, d.H, d.T, Hp[i]);
+      VI_HIP(vi::compact(b->st, c->o_bd, d.V, c->o_pl, c->d_count, c->ctemp, c->ctemp_bytes));
+      VI_HIP(vi::compact(b->st, c->o_S, d.V, c->o_tl, c->d_count + 1, c->ctemp, c->ctemp_bytes));
+      VI_HIP(hipMemcpyAsync(&cnt[2 * i], c->d_count, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                            b->st));
+    }
+    VI_TRY(launched("onion layer"));
+    VI_HIP(hipStreamSynchronize(b->st));
+    std::vector<vi_ctx*> next;
+    std::vector<uint8_t*> nH, nE;
+    b->h_jobs.clear();
+    for (size_t i = 0; i < active.size(); ++i) {
+      vi_ctx* c = active[i];
+      if (cnt[2 * i] == 0) {  // H' is empty: this clip's peel is finished
+        c->lv[c->L - 1].complete = false;
+        c->phase = 1;
+        c->cur_level = c->L - 1;
+        c->em_k = 0;
+        continue;
+      }
+      const int32_t level = c->L - 1;
+      vi::JobDesc J = job_for(b, c, level, b->h_jobs.size(), false);
+      J.tlist = c->o_tl;
+      J.nS = cnt[2 * i + 1];
+      J.hlist = c->o_pl;
+      J.nH = cnt[2 * i];
+      J.smask = c->o_S;
+      J.excl = Hp[i];
+      J.step = (uint64_t(1) << 32) + (uint64_t)layer;
+      J.evals = c->d_u64 + 5;
+      J.evals_init = c->d_u64 + 5;
+      c->n_nominal += per_target_evals(c->prm, r_max(c->lv[level].d)) * (int64_t)J.nS;
+      c->n_searches += 1;
+      c->n_recon += J.nH;
+      b->h_jobs.push_back(J);
+      next.push_back(c);
+      nH.push_back(E[i]);  // H' <- erosion for the next layer
+      nE.push_back(Hp[i]);
+    }
+    if (!b->h_jobs.empty()) {
+      VI_TRY(batch_upload(b, blk));
+      VI_TRY(batch_enqueue_iteration(b, true));
+    }
+    active.swap(next);
+    Hp.swap(nH);
+    E.swap(nE);
+  }
+  b->blk = saved_blk;
+  b->grid_mult = saved_mult;
+  return VI_OK;
 }
 
 // Times one propagation pass (reading buffer 0, writing buffer 1, which the
@@ -891,7 +1013,7 @@ vi_status batch_enqueue_iteration(vi_batch* b) {
 // current state and EM index.
 vi_status batch_autotune(vi_batch* b) {
   static const int kBlk[3] = {64, 128, 256};
-  static const int kMult[3] = {2, 4, 8};
+  static const int kMult[4] = {0, 2, 4, 8};  // 0: direct launches
   hipEvent_t e0, e1;
   VI_HIP(hipEventCreate(&e0));
   VI_HIP(hipEventCreate(&e1));
@@ -902,14 +1024,20 @@ vi_status batch_autotune(vi_batch* b) {
     if ((st = batch_build(b, kBlk[ib], true)) != VI_OK) break;
     const vi::BatchArgs B = batch_args(b);
     vi::launch_batch_zero(b->st, B, b->cap_jobs);
-    vi::launch_batch_s0(b->st, B, kBlk[ib], b->ncu * 4, 0);
-    for (int im = 0; im < 3; ++im) {
-      const int32_t grid = b->ncu * kMult[im];
+    // step 0 over every target chunk (direct: one workgroup per chunk)
+    vi::BatchArgs B0 = B;
+    B0.direct = 1;
+    vi::launch_batch_s0(b->st, B0, kBlk[ib], std::max<int32_t>(1, (int32_t)b->h_tj.size()), 0);
+    for (int im = 0; im < 4; ++im) {
+      vi::BatchArgs Bm = B;
+      Bm.direct = kMult[im] == 0 ? 1 : 0;
+      const int32_t grid = Bm.direct ? (int32_t)b->h_tj.size() : b->ncu * kMult[im];
       const int32_t s = b->sched.n_jf > 0 ? b->sched.jf_steps[0] : 1;
-      vi::launch_batch_pass(b->st, B, kBlk[ib], grid, s, 1, 0, 1 + 4 * im);
+      if (grid <= 0) continue;
+      vi::launch_batch_pass(b->st, Bm, kBlk[ib], grid, s, 1, 0, 1 + 4 * im);
       (void)hipEventRecord(e0, b->st);
       for (int r = 0; r < 3; ++r)
-        vi::launch_batch_pass(b->st, B, kBlk[ib], grid, s, 1, 0, 2 + 4 * im + r);
+        vi::launch_batch_pass(b->st, Bm, kBlk[ib], grid, s, 1, 0, 2 + 4 * im + r);
       (void)hipEventRecord(e1, b->st);
       if ((st = launched("autotune")) != VI_OK) break;
       if (hipEventSynchronize(e1) != hipSuccess) {
@@ -944,8 +1072,8 @@ vi_status vi_batch_create(vi_batch** out, const vi_tune* tune, void* hip_stream)
   if (tune && tune->tuned) {
     if (tune->block != 64 && tune->block != 128 && tune->block != 256)
       return fail(VI_E_INVAL, "tune.block must be 64, 128 or 256");
-    if (tune->grid_mult < 1 || tune->grid_mult > 64)
-      return fail(VI_E_INVAL, "tune.grid_mult must be in [1, 64]");
+    if (tune->grid_mult < 0 || tune->grid_mult > 64)
+      return fail(VI_E_INVAL, "tune.grid_mult must be in [0, 64]");
   }
   vi_batch* b = new (std::nothrow) vi_batch();
   if (!b) return fail(VI_E_NOMEM, "host allocation failed");
@@ -987,12 +1115,17 @@ vi_status vi_batch_create(vi_batch** out, const vi_tune* tune, void* hip_stream)
   b->d_tchunk_job = static_cast<int32_t*>(alloc(sizeof(int32_t) * (size_t)b->cap_tchunks));
   b->d_pchunk_job = static_cast<int32_t*>(alloc(sizeof(int32_t) * (size_t)b->cap_pchunks));
   b->d_counts = static_cast<int32_t*>(alloc(sizeof(int32_t) * 4));
+  if (hipHostMalloc((void**)&b->h_abs, sizeof(unsigned long long) * b->cap_jobs,
+                    hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    b->h_abs = nullptr;
+  }
   b->d_abs = static_cast<unsigned long long*>(alloc(sizeof(unsigned long long) * b->cap_jobs));
   b->d_scratch = static_cast<unsigned long long*>(alloc(sizeof(unsigned long long) * 8));
   b->d_queue = static_cast<int32_t*>(alloc(sizeof(int32_t) * vi::kQueueSlots));
   (void)p;
   if (!b->d_jobs || !b->d_tchunk_job || !b->d_pchunk_job || !b->d_counts || !b->d_abs ||
-      !b->d_scratch || !b->d_queue) {
+      !b->d_scratch || !b->d_queue || !b->h_abs) {
     vi_batch_destroy(b);
     return fail(VI_E_NOMEM, "batch allocation failed");
   }
@@ -1058,17 +1191,21 @@ vi_status vi_batch_step(vi_batch* b, int32_t* n_done) {
   if (!b) return fail(VI_E_INVAL, "null batch");
   if (n_done) *n_done = 0;
   int32_t done = 0;
-  // clips that have not started: onion peel of their coarsest level
-  for (vi_ctx* c : b->members) {
-    if (c->phase == 0) VI_TRY(drive_start(c));
-    VI_TRY(drive_skip_empty(c));
-  }
+  // clips that have not started: onion peels of their coarsest levels,
+  // layer by layer for all of them together
+  std::vector<vi_ctx*> fresh;
+  for (vi_ctx* c : b->members)
+    if (c->phase == 0) fresh.push_back(c);
+  if (!fresh.empty()) VI_TRY(batch_onion(b, fresh));
+  for (vi_ctx* c : b->members) VI_TRY(drive_skip_empty(c));
   bool any = false;
   for (vi_ctx* c : b->members) any = any || c->phase == 1;
   if (any) {
     if (!b->tuned) VI_TRY(batch_autotune(b));
     VI_TRY(batch_build(b, b->blk, false));
-    if (!b->exec) {
+    if (b->grid_mult == 0) {
+      VI_TRY(batch_enqueue_iteration(b));
+    } else if (!b->exec) {
       VI_HIP(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
       const vi_status cs = batch_enqueue_iteration(b);
       hipGraph_t g = nullptr;
@@ -1079,12 +1216,17 @@ vi_status vi_batch_step(vi_batch* b, int32_t* n_done) {
       b->graph = g;
       VI_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     }
-    VI_HIP(hipGraphLaunch(b->exec, b->st));
+    if (b->grid_mult != 0) VI_HIP(hipGraphLaunch(b->exec, b->st));
     const size_t nj = b->h_jobs.size();
-    b->h_abs.assign(nj, 0);
-    VI_HIP(hipMemcpyAsync(b->h_abs.data(), b->d_abs, sizeof(unsigned long long) * nj,
-                          hipMemcpyDeviceToHost, b->st));
-    VI_HIP(hipStreamSynchronize(b->st));
+    // the stopping test needs this step's |change| sums; clips with a fixed
+    // number of iterations (em_tol < 0) need no read-back
+    bool need_abs = false;
+    for (size_t j = 0; j < nj; ++j) need_abs = need_abs || b->job_ctx[j]->prm.em_tol >= 0;
+    if (need_abs) {
+      VI_HIP(hipMemcpyAsync(b->h_abs, b->d_abs, sizeof(unsigned long long) * nj,
+                            hipMemcpyDeviceToHost, b->st));
+      VI_HIP(hipStreamSynchronize(b->st));
+    }
     ++b->steps_run;
     for (size_t j = 0; j < nj; ++j) {
       vi_ctx* c = b->job_ctx[j];
@@ -1094,7 +1236,7 @@ vi_status vi_batch_step(vi_batch* b, int32_t* n_done) {
       c->n_em += 1;
       c->n_recon += lv.nH;
       c->em_k += 1;
-      const double e = (double)b->h_abs[j] / (3.0 * (double)lv.nH);
+      const double e = c->prm.em_tol >= 0 ? (double)b->h_abs[j] / (3.0 * (double)lv.nH) : INFINITY;
       if (!(e > c->prm.em_tol && c->em_k < c->prm.em_max_iters)) {
         VI_TRY(drive_finish_level(c));
         VI_TRY(drive_skip_empty(c));
@@ -1102,7 +1244,7 @@ vi_status vi_batch_step(vi_batch* b, int32_t* n_done) {
     }
   }
   for (vi_ctx* c : b->members) done += c->phase == 2 ? 1 : 0;
-  VI_HIP(hipStreamSynchronize(b->st));
+  VI_TRY(launched("batch step"));
   if (n_done) *n_done = done;
   return VI_OK;
 }

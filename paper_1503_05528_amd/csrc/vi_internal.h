@@ -81,6 +81,8 @@ struct JobDesc {
   int32_t pchunk0;  // first pixel chunk
   int32_t recon_mode;
   int32_t pad_;
+  const uint8_t* smask;  // target-set membership (masked launches: onion layer)
+  const uint8_t* excl;   // voxels excluded from comparisons and votes (onion: H')
   uint64_t step;    // EM index at the level (Philox counter word 1)
   unsigned long long* absdiff;
   unsigned long long* evals;       // distances computed by the passes
@@ -97,7 +99,8 @@ struct BatchArgs {
   const int32_t* tchunk_job;  // job of every target chunk
   const int32_t* pchunk_job;  // job of every pixel chunk
   const int32_t* counts;      // [0] target chunks, [1] pixel chunks, [2] jobs
-  int32_t* queue;             // [kQueueSlots] next chunk of each launch
+  int32_t* queue;             // [kQueueSlots] next chunk of each persistent launch
+  int32_t direct;             // 1: one workgroup per chunk (grid = chunk count)
 };
 
 // ---------------------------------------------------------------- launchers
@@ -134,16 +137,20 @@ void launch_set_state(hipStream_t st, DevLevel L, const uint8_t* rgbt, const int
                       const int32_t* dist, const uint8_t* nvox, unsigned long long* bad);
 void launch_out_rgb(hipStream_t st, DevLevel L0, uint8_t* out);
 
-// batched, persistent launches over every job's chunks (grid = `grid` blocks;
-// blk = targets per workgroup, 64, 128 or 256)
+// batched launches over every job's chunks: persistent (grid = `grid`
+// workgroups taking chunks from a counter) or direct (B.direct, grid = the
+// chunk count); blk = targets per workgroup, 64, 128 or 256
 // `slot` selects the chunk counter of the launch; launch_batch_zero clears
 // the counters and the per-job outputs at the start of an iteration
 void launch_batch_zero(hipStream_t st, const BatchArgs& B, int32_t max_jobs);
-void launch_batch_s0(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t slot);
+// masked: the onion peel's partial distance (J.excl) and target sets (J.smask)
+void launch_batch_s0(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t slot,
+                     bool masked = false);
 void launch_batch_pass(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t s,
-                       int32_t k, int32_t parity, int32_t slot);
+                       int32_t k, int32_t parity, int32_t slot, bool masked = false);
 void launch_batch_copy(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t slot);
-void launch_batch_recon(hipStream_t st, const BatchArgs& B, int32_t grid, int32_t slot);
+void launch_batch_recon(hipStream_t st, const BatchArgs& B, int32_t grid, int32_t slot,
+                        bool masked = false);
 
 // stream compaction (stable): out[k] = i for the k-th i with flags[i] != 0
 size_t compact_temp_bytes(int32_t n);

@@ -398,7 +398,9 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
     const int slot = (int)(key & 7);
     uint32_t best_d = (uint32_t)(key >> 3);
     int32_t best_c = slot ? s_cand[tid * 6 + slot - 1] : inc.x;
-    if (A.rs_k > 0) {
+    // best_c >= 0 for every target once step 0 has run; a target without a
+    // match (cand -1) is left to step 0 rather than searched around
+    if (A.rs_k > 0 && best_c >= 0) {
       int32_t cx, cy, ct;
       unlin(L, best_c, cx, cy, ct);
       const int32_t R = A.R;
@@ -412,12 +414,15 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
       const int32_t ry = loy + draw_below(w[1], (uint32_t)(hiy - loy + 1));
       const int32_t rt = lot + draw_below(w[2], (uint32_t)(hit - lot + 1));
       const int32_t rc = (rt * L.H + ry) * L.W + rx;
-      // strictly better only: nothing beats distance 0
-      const int nr = (best_d != 0 && rc != best_c && L.dsrc[rc]) ? 1 : 0;
+      // strictly better only: nothing beats distance 0.  The window keeps the
+      // whole candidate patch inside the volume, so the distance can be
+      // computed before the source test, which is only needed (and its
+      // random byte fetched) when the candidate would win.
+      const int nr = (best_d != 0 && rc != best_c) ? 1 : 0;
       if (nr) {
         int32_t n;
         const uint32_t d = patch_ssd<MASKED, true>(L, A.excl, p, px, py, pt, rc, best_d - 1u, n);
-        if (d < best_d) {
+        if (d < best_d && L.dsrc[rc]) {
           best_d = d;
           best_c = rc;
         }
@@ -698,12 +703,37 @@ __global__ __launch_bounds__(kBlock) void k_recon(DevLevel L, const int32_t* __r
 // workgroup takes which chunk.  Chunk counts are read from device memory, so
 // a captured graph of these launches stays valid when jobs come and go.
 // ------------------------------------------------------------------------
-__device__ __forceinline__ int32_t next_chunk(int32_t* counter, int32_t& s_c) {
+// Chunk scheduler.  Direct launches (grid = number of chunks) map workgroup
+// b to chunk xcd_block(b), like the single-clip kernels.  Persistent
+// launches (a fixed grid, as captured in a graph) take chunks from one
+// counter per launch in increasing order: chunks of different jobs and
+// levels cost very different amounts, so a static split would leave the
+// launch waiting for its slowest workgroup.
+struct ChunkCursor {
+  int32_t c;
+  bool first;
+};
+
+__device__ __forceinline__ bool next_chunk(int32_t* counter, int32_t n, bool direct,
+                                           ChunkCursor& cur, int32_t* s_c) {
+  if (direct) {
+    // block b takes chunks xcd_block(b) + k * grid: every chunk is covered
+    // whatever the grid (one chunk per workgroup when grid = n)
+    cur.c = cur.first ? xcd_block(blockIdx.x, gridDim.x) : cur.c + (int32_t)gridDim.x;
+    cur.first = false;
+    return cur.c < n;
+  }
   __syncthreads();  // every thread has read the previous chunk index
-  if (threadIdx.x == 0) s_c = atomicAdd(counter, 1);
+  if (threadIdx.x == 0) *s_c = atomicAdd(counter, 1);
   __syncthreads();
-  return s_c;
+  cur.c = *s_c;
+  return cur.c < n;
 }
+
+#define FOR_EACH_CHUNK(counter, n, direct, c)                   \
+  __shared__ int32_t s_cur_;                                    \
+  ChunkCursor cur_{0, true};                                    \
+  for (int32_t c = 0; next_chunk(counter, n, direct, cur_, &s_cur_) && ((c = cur_.c), true);)
 
 __global__ void kb_zero(BatchArgs B) {
   const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -711,70 +741,80 @@ __global__ void kb_zero(BatchArgs B) {
   if (j < kQueueSlots) B.queue[j] = 0;
 }
 
-template <int BLK>
+template <int BLK, bool MASKED>
 __global__ __launch_bounds__(BLK) void kb_s0(BatchArgs B, int32_t slot) {
-  __shared__ int32_t s_c;
   const int32_t n = B.counts[0];
-  for (int32_t c = next_chunk(B.queue + slot, s_c); c < n; c = next_chunk(B.queue + slot, s_c)) {
-    const JobDesc& J = B.jobs[B.tchunk_job[c]];
+  FOR_EACH_CHUNK(B.queue + slot, n, B.direct, c) {
+    // a private copy: the descriptor stays in scalar registers in the hot loops
+    const JobDesc& Jg = B.jobs[B.tchunk_job[c]];
+    const DevLevel L = Jg.L;
+    const JobDesc& J = Jg;
     PassArgs A{};
     A.tlist = J.tlist;
     A.nS = J.nS;
-    A.nin = J.L.nnf0;
+    A.excl = J.excl;
+    A.nin = L.nnf0;
     A.step = J.step;
-    const int ne = s0_target<false>(J.L, A, (c - J.tchunk0) * BLK + (int32_t)threadIdx.x);
+    const int ne = s0_target<MASKED>(L, A, (c - J.tchunk0) * BLK + (int32_t)threadIdx.x);
     count_evals(J.evals_init, ne);
   }
 }
 
-template <int BLK>
+template <int BLK, bool MASKED>
 __global__ __launch_bounds__(BLK) void kb_pass(BatchArgs B, int32_t s, int32_t k, int32_t parity,
                                                int32_t slot) {
   __shared__ PassShared<BLK> sh;
-  __shared__ int32_t s_c;
   const int32_t n = B.counts[0];
-  for (int32_t c = next_chunk(B.queue + slot, s_c); c < n; c = next_chunk(B.queue + slot, s_c)) {
-    const JobDesc& J = B.jobs[B.tchunk_job[c]];
+  FOR_EACH_CHUNK(B.queue + slot, n, B.direct, c) {
+    // a private copy: the descriptor stays in scalar registers in the hot loops
+    const JobDesc& Jg = B.jobs[B.tchunk_job[c]];
+    const DevLevel L = Jg.L;
+    const JobDesc& J = Jg;
     PassArgs A{};
     A.tlist = J.tlist;
     A.nS = J.nS;
-    A.smask = J.L.htil;
-    A.nin = parity ? J.L.nnf1 : J.L.nnf0;
-    A.nout = parity ? J.L.nnf0 : J.L.nnf1;
+    A.smask = MASKED ? J.smask : L.htil;
+    A.excl = J.excl;
+    A.nin = parity ? L.nnf1 : L.nnf0;
+    A.nout = parity ? L.nnf0 : L.nnf1;
     A.s = s;
     A.R = J.R[k];
     A.rs_k = (k > 0 && A.R >= 1) ? k : 0;
     A.step = J.step;
-    const int ne = pass_block<BLK, false>(J.L, A, c - J.tchunk0, sh);
+    const int ne = pass_block<BLK, MASKED>(L, A, c - J.tchunk0, sh);
     count_evals(J.evals, ne);
   }
 }
 
 template <int BLK>
 __global__ __launch_bounds__(BLK) void kb_copy(BatchArgs B, int32_t slot) {
-  __shared__ int32_t s_c;
   const int32_t n = B.counts[0];
-  for (int32_t c = next_chunk(B.queue + slot, s_c); c < n; c = next_chunk(B.queue + slot, s_c)) {
-    const JobDesc& J = B.jobs[B.tchunk_job[c]];
+  FOR_EACH_CHUNK(B.queue + slot, n, B.direct, c) {
+    // a private copy: the descriptor stays in scalar registers in the hot loops
+    const JobDesc& Jg = B.jobs[B.tchunk_job[c]];
+    const DevLevel L = Jg.L;
+    const JobDesc& J = Jg;
     const int32_t i = (c - J.tchunk0) * BLK + (int32_t)threadIdx.x;
-    if (i < J.nS) J.L.nnf0[J.tlist[i]] = J.L.nnf1[J.tlist[i]];
+    if (i < J.nS) L.nnf0[J.tlist[i]] = L.nnf1[J.tlist[i]];
   }
 }
 
+template <bool FILT>
 __global__ __launch_bounds__(kBlock) void kb_recon(BatchArgs B, int32_t slot) {
   constexpr int kWaves = kBlock / 64;
-  __shared__ int32_t s_c;
   const int32_t n = B.counts[1];
-  for (int32_t c = next_chunk(B.queue + slot, s_c); c < n; c = next_chunk(B.queue + slot, s_c)) {
-    const JobDesc& J = B.jobs[B.pchunk_job[c]];
+  FOR_EACH_CHUNK(B.queue + slot, n, B.direct, c) {
+    const JobDesc& Jg = B.jobs[B.pchunk_job[c]];
+    const DevLevel L = Jg.L;
+    const JobDesc& J = Jg;
     const int32_t base = (c - J.pchunk0) * kPixChunk;
     const int32_t end = min(J.nH, base + kPixChunk);
     unsigned long long my_abs = 0;
     for (int32_t w = base + (int32_t)(threadIdx.x >> 6); w < end; w += kWaves) {
       if (J.recon_mode == 1)
-        recon_pixel<1, false>(J.L, J.hlist, w, nullptr, nullptr, my_abs);
+        recon_pixel<1, FILT>(L, J.hlist, w, J.excl, nullptr, my_abs);
       else
-        recon_pixel<0, false>(J.L, J.hlist, w, nullptr, nullptr, my_abs);
+        recon_pixel<0, FILT>(L, J.hlist, w, J.excl, nullptr, my_abs);
     }
     if ((threadIdx.x & 63) == 0 && my_abs) atomicAdd(J.absdiff, my_abs);
   }
@@ -1187,23 +1227,41 @@ void launch_batch_zero(hipStream_t st, const BatchArgs& B, int32_t max_jobs) {
   kb_zero<<<dim3((unsigned)((n + 255) / 256)), 256, 0, st>>>(B);
 }
 
-void launch_batch_s0(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t slot) {
+template <bool M>
+static void batch_s0(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t slot) {
   if (blk == 64)
-    kb_s0<64><<<grid, 64, 0, st>>>(B, slot);
+    kb_s0<64, M><<<grid, 64, 0, st>>>(B, slot);
   else if (blk == 128)
-    kb_s0<128><<<grid, 128, 0, st>>>(B, slot);
+    kb_s0<128, M><<<grid, 128, 0, st>>>(B, slot);
   else
-    kb_s0<256><<<grid, 256, 0, st>>>(B, slot);
+    kb_s0<256, M><<<grid, 256, 0, st>>>(B, slot);
+}
+
+void launch_batch_s0(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t slot,
+                     bool masked) {
+  if (masked)
+    batch_s0<true>(st, B, blk, grid, slot);
+  else
+    batch_s0<false>(st, B, blk, grid, slot);
+}
+
+template <bool M>
+static void batch_pass(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t s,
+                       int32_t k, int32_t parity, int32_t slot) {
+  if (blk == 64)
+    kb_pass<64, M><<<grid, 64, 0, st>>>(B, s, k, parity, slot);
+  else if (blk == 128)
+    kb_pass<128, M><<<grid, 128, 0, st>>>(B, s, k, parity, slot);
+  else
+    kb_pass<256, M><<<grid, 256, 0, st>>>(B, s, k, parity, slot);
 }
 
 void launch_batch_pass(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t s,
-                       int32_t k, int32_t parity, int32_t slot) {
-  if (blk == 64)
-    kb_pass<64><<<grid, 64, 0, st>>>(B, s, k, parity, slot);
-  else if (blk == 128)
-    kb_pass<128><<<grid, 128, 0, st>>>(B, s, k, parity, slot);
+                       int32_t k, int32_t parity, int32_t slot, bool masked) {
+  if (masked)
+    batch_pass<true>(st, B, blk, grid, s, k, parity, slot);
   else
-    kb_pass<256><<<grid, 256, 0, st>>>(B, s, k, parity, slot);
+    batch_pass<false>(st, B, blk, grid, s, k, parity, slot);
 }
 
 void launch_batch_copy(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t slot) {
@@ -1215,8 +1273,12 @@ void launch_batch_copy(hipStream_t st, const BatchArgs& B, int blk, int32_t grid
     kb_copy<256><<<grid, 256, 0, st>>>(B, slot);
 }
 
-void launch_batch_recon(hipStream_t st, const BatchArgs& B, int32_t grid, int32_t slot) {
-  kb_recon<<<grid, kBlock, 0, st>>>(B, slot);
+void launch_batch_recon(hipStream_t st, const BatchArgs& B, int32_t grid, int32_t slot,
+                        bool masked) {
+  if (masked)
+    kb_recon<true><<<grid, kBlock, 0, st>>>(B, slot);
+  else
+    kb_recon<false><<<grid, kBlock, 0, st>>>(B, slot);
 }
 
 }  // namespace vi

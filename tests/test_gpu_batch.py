@@ -46,7 +46,7 @@ def references(vi):
     return [alone(vi, c, kw) for c, kw in clips()]
 
 
-@pytest.mark.parametrize("tune", [None, (64, 2), (128, 1), (256, 8)])
+@pytest.mark.parametrize("tune", [None, (64, 2), (128, 1), (256, 8), (256, 0), (64, 0)])
 def test_batch_matches_alone(vi, references, tune):
     print(f"[case] batch tune={tune}", flush=True)
     b = vi.Batch(tune=tune)
@@ -62,6 +62,28 @@ def test_batch_matches_alone(vi, references, tune):
     for g, ref in zip(members, references):
         assert g.done()
         assert np.array_equal(g.output().cpu().numpy(), ref)
+
+
+def test_autotune_covers_every_target_chunk(vi):
+    # 4 clips with ~45k coarse targets each: 2845 chunks of 64 targets, more
+    # than the persistent grid of the tuner's step 0 would cover, so any
+    # target that step 0 skipped would reach the passes without a match
+    print("[case] autotune with 2845 target chunks at block 64", flush=True)
+    cs = [(synth.small(40 + s, 256, 192, 32, levels=2, frac=0.08),
+           dict(levels=2, seed=20 + s, em_tol=-1.0, em_max_iters=2)) for s in range(4)]
+    refs = [alone(vi, c, kw) for c, kw in cs]
+    b = vi.Batch()
+    members = []
+    for c, kw in cs:
+        g = vi.Clip(dev(c.occluded_input()), dev(c.mask), **kw)
+        b.add(g)
+        members.append(g)
+    b.run()
+    assert b.tune() is not None
+    for g, ref in zip(members, refs):
+        assert np.array_equal(g.output().cpu().numpy(), ref)
+        g.close()
+    b.close()
 
 
 def test_clips_joining_a_running_batch(vi, references):
