@@ -47,6 +47,10 @@ def parse():
     ap.add_argument("--served-rate", type=float, default=4.0)
     ap.add_argument("--summarize-counters", metavar="DIR",
                     help="summarise a rocprofv3 --output-format csv directory and exit")
+    ap.add_argument("--assemble-counters", nargs=4,
+                    metavar=("PASS_FETCH", "PASS_WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="write the search kernel's HBM traffic record from four "
+                         "--summarize-counters outputs (JSON files) and exit")
     return ap.parse_args()
 
 
@@ -85,6 +89,57 @@ def summarize_counters(d):
                     "mean_us": sum(ds) / len(ds) / 1000.0,
                     "counters": {c: sum(v) / len(v) for c, v in sorted(a["counters"].items())}})
     return out
+
+
+PASS_KERNEL = "vi::k_pass<false>"
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+COPY_BYTES = 1 << 30
+
+
+def assemble_counters(pass_fetch, pass_write, copy_fetch, copy_write, workload):
+    """HBM bytes per launch of the search kernel: FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch, averaged over every dispatch of the kernel at every
+    grid size) scaled by what the same counters read for a plain 1 GiB
+    device copy, which reads and writes exactly COPY_BYTES."""
+    def load(path, kernel, counter):
+        rows = [r for r in json.load(open(path)) if r["kernel"] == kernel]
+        n = sum(r["dispatches"] for r in rows)
+        if n == 0:
+            raise SystemExit(f"{path}: no dispatch of {kernel}")
+        v = sum(r["counters"][counter] * r["dispatches"] for r in rows) / n
+        us = sum(r["mean_us"] * r["dispatches"] for r in rows) / n
+        return v, us, n
+    fk, us, n = load(pass_fetch, PASS_KERNEL, "FETCH_SIZE")
+    wk, _, _ = load(pass_write, PASS_KERNEL, "WRITE_SIZE")
+    cf, cus, _ = load(copy_fetch, COPY_KERNEL, "FETCH_SIZE")
+    cw, _, _ = load(copy_write, COPY_KERNEL, "WRITE_SIZE")
+    fscale = COPY_BYTES / 1024.0 / cf
+    wscale = COPY_BYTES / 1024.0 / cw
+    rec = {
+        "kernel": PASS_KERNEL, "workload": workload, "source_sha256": kernel_source_hash(),
+        "fetch_kib_per_launch": fk, "write_kib_per_launch": wk,
+        "fetch_scale": fscale, "write_scale": wscale,
+        "hbm_bytes_per_launch": 1024.0 * (fk * fscale + wk * wscale),
+        "mean_launch_us": us, "dispatches": n,
+        "copy_calibration": {"bytes": COPY_BYTES, "FETCH_SIZE_kib": cf, "WRITE_SIZE_kib": cw,
+                             "mean_us": cus},
+        "commands": [
+            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --kernel-include-regex k_pass "
+            "--output-format csv -d /tmp/p_FETCH_SIZE -o run -- python $REPO/bench.py "
+            "--no-cpu-baseline --no-batched --no-served --steps 1 --warmup 0",
+            "(the same with WRITE_SIZE)",
+            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv "
+            "-d /tmp/c_FETCH_SIZE -o run -- python $REPO/bench.py --copy-calibration "
+            "(and the same with WRITE_SIZE)",
+            "python $REPO/bench.py --summarize-counters <dir> > <json>   (each of the four)",
+            "python $REPO/bench.py --assemble-counters <pass FETCH> <pass WRITE> "
+            "<copy FETCH> <copy WRITE>",
+        ],
+    }
+    with open(COUNTERS_JSON, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    return rec
 
 
 def _gen_batch_clip(seed):
@@ -264,6 +319,9 @@ def main():
     a = parse()
     if a.summarize_counters:
         print(json.dumps(summarize_counters(a.summarize_counters), indent=1))
+        return
+    if a.assemble_counters:
+        print(json.dumps(assemble_counters(*a.assemble_counters, a.config), indent=1))
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
