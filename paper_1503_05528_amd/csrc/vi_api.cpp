@@ -61,13 +61,15 @@ struct vi_ctx {
   void* ctemp = nullptr;  // compaction scratch
   size_t ctemp_bytes = 0;
   int32_t* d_count = nullptr;             // [2]
-  unsigned long long* d_u64 = nullptr;    // [0] absdiff, [1..2] set_state checks,
-                                          // [3..5] evaluations: passes, step 0, onion
+  unsigned long long* d_u64 = nullptr;    // [0] |change| sum, [1..2] set_state checks,
+                                          // [3..5] evaluation sums: passes, step 0, onion
+  unsigned long long* d_cnt = nullptr;    // spread counters (kCntWords words each):
+                                          // [0] |change|, [1..3] evaluations as d_u64[3..5]
   // onion-peel scratch (coarsest level)
   uint8_t *o_Hp = nullptr, *o_E = nullptr, *o_bd = nullptr, *o_S = nullptr;
   uint8_t *o_t1 = nullptr, *o_t2 = nullptr;
   int32_t *o_tl = nullptr, *o_pl = nullptr;
-  // work counters (host side; effective evaluations live in d_u64[3])
+  // work counters (host side; effective evaluations live in d_cnt[1..3])
   int64_t n_nominal = 0, n_searches = 0, n_em = 0, n_recon = 0;
   // kernel timing with events on the context's stream
   bool profiling = false;
@@ -242,8 +244,8 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
   A.excl = excl;
   A.step = step;
   // onion searches (masked) count apart from the EM loop's
-  unsigned long long* ev_pass = c->d_u64 + (excl ? 5 : 3);
-  unsigned long long* ev_init = c->d_u64 + (excl ? 5 : 4);
+  unsigned long long* ev_pass = c->d_cnt + (size_t)(excl ? 3 : 1) * vi::kCntWords;
+  unsigned long long* ev_init = c->d_cnt + (size_t)(excl ? 3 : 2) * vi::kCntWords;
   A.evals = ev_init;
   A.nin = d.nnf0;
   A.nout = d.nnf0;
@@ -282,13 +284,17 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
   return VI_OK;
 }
 
+// absdiff (optional, one word of device memory) receives the pixels' |change|
+// sum, gathered in the spread counter d_cnt[0]
 vi_status recon(vi_ctx* c, int32_t level, const int32_t* plist, int32_t nP, const uint8_t* excl,
                 int mode, float* out_f, unsigned long long* absdiff) {
-  if (absdiff) vi::launch_fill_u64(c->st, absdiff, 1);
+  unsigned long long* spread = absdiff ? c->d_cnt : nullptr;
+  if (spread) vi::launch_fill_u64(c->st, spread, vi::kCntWords);
   c->n_recon += nP;
   const int r = prof_begin(c);
-  vi::launch_recon(c->st, c->lv[level].d, plist, nP, excl, mode, out_f, absdiff);
+  vi::launch_recon(c->st, c->lv[level].d, plist, nP, excl, mode, out_f, spread);
   prof_end(c, r, VI_K_RECON, level, nP);
+  if (spread) vi::launch_sum_spread(c->st, spread, 1, absdiff);
   return launched("recon");
 }
 
@@ -486,8 +492,11 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
   }
   const vi::DevLevel& L0 = c->lv[0].d;
   const size_t V0 = (size_t)L0.V;
-  if ((st = dalloc(c, &c->d_count, 4)) || (st = dalloc(c, &c->d_u64, 8))) return bail(st);
+  if ((st = dalloc(c, &c->d_count, 4)) || (st = dalloc(c, &c->d_u64, 8)) ||
+      (st = dalloc(c, &c->d_cnt, 4 * (size_t)vi::kCntWords)))
+    return bail(st);
   vi::launch_fill_u64(c->st, c->d_u64, 8);
+  vi::launch_fill_u64(c->st, c->d_cnt, 4 * vi::kCntWords);
   c->ctemp_bytes = vi::compact_temp_bytes(L0.V);
   if ((st = dalloc(c, reinterpret_cast<uint8_t**>(&c->ctemp), c->ctemp_bytes))) return bail(st);
   // creation temporaries
@@ -665,6 +674,8 @@ int64_t vi_nominal_evals(const vi_ctx* c, int32_t level) {
 vi_status vi_get_counters(vi_ctx* c, vi_counters* out) {
   if (!c || !out) return fail(VI_E_INVAL, "null argument");
   unsigned long long v[3] = {0, 0, 0};
+  vi::launch_sum_spread(c->st, c->d_cnt + vi::kCntWords, 3, c->d_u64 + 3);
+  VI_TRY(launched("counters"));
   VI_HIP(hipMemcpyAsync(v, c->d_u64 + 3, sizeof(v), hipMemcpyDeviceToHost, c->st));
   VI_TRY(sync(c));
   out->nominal_evals = c->n_nominal;
@@ -681,7 +692,7 @@ vi_status vi_get_counters(vi_ctx* c, vi_counters* out) {
 vi_status vi_reset_counters(vi_ctx* c) {
   if (!c) return fail(VI_E_INVAL, "null context");
   c->n_nominal = c->n_searches = c->n_em = c->n_recon = 0;
-  vi::launch_fill_u64(c->st, c->d_u64 + 3, 3);
+  vi::launch_fill_u64(c->st, c->d_cnt + vi::kCntWords, 3 * vi::kCntWords);
   return launched("fill");
 }
 
@@ -769,7 +780,8 @@ struct vi_batch {
   int32_t* d_pchunk_job = nullptr;
   int32_t* d_counts = nullptr;
   unsigned long long* d_abs = nullptr;
-  unsigned long long* d_scratch = nullptr;
+  unsigned long long* d_scratch = nullptr;     // spread counter of the tuner's launches
+  unsigned long long* d_abs_spread = nullptr;  // cap_jobs spread |change| counters
   int32_t* d_queue = nullptr;
   std::vector<vi::JobDesc> h_jobs;
   std::vector<int32_t> h_tj, h_pj;
@@ -796,7 +808,8 @@ void batch_free(vi_batch* b) {
   b->exec = nullptr;
   b->graph = nullptr;
   for (void* p : {(void*)b->d_jobs, (void*)b->d_tchunk_job, (void*)b->d_pchunk_job,
-                  (void*)b->d_counts, (void*)b->d_abs, (void*)b->d_scratch, (void*)b->d_queue})
+                  (void*)b->d_counts, (void*)b->d_abs, (void*)b->d_scratch, (void*)b->d_queue,
+                  (void*)b->d_abs_spread})
     if (p) (void)hipFree(p);
   b->d_queue = nullptr;
   for (auto& st : b->stage) {
@@ -809,7 +822,7 @@ void batch_free(vi_batch* b) {
   b->h_abs = nullptr;
   b->d_jobs = nullptr;
   b->d_tchunk_job = b->d_pchunk_job = b->d_counts = nullptr;
-  b->d_abs = b->d_scratch = nullptr;
+  b->d_abs = b->d_scratch = b->d_abs_spread = nullptr;
 }
 
 
@@ -875,9 +888,9 @@ vi::JobDesc job_for(vi_batch* b, vi_ctx* c, int32_t level, size_t slot, bool scr
   J.nH = lv.nH;
   J.recon_mode = c->prm.recon_mode;
   J.step = (uint64_t)c->em_k;
-  J.absdiff = b->d_abs + slot;
-  J.evals = scratch_evals ? b->d_scratch : c->d_u64 + 3;
-  J.evals_init = scratch_evals ? b->d_scratch : c->d_u64 + 4;
+  J.absdiff = b->d_abs_spread + slot * (size_t)vi::kCntWords;
+  J.evals = scratch_evals ? b->d_scratch : c->d_cnt + vi::kCntWords;
+  J.evals_init = scratch_evals ? b->d_scratch : c->d_cnt + 2 * (size_t)vi::kCntWords;
   const int32_t rmax = r_max(lv.d);
   for (int k = 0; k <= vi::kMaxPmIters; ++k) J.R[k] = k == 0 ? 0 : rs_radius(c->prm, rmax, k);
   return J;
@@ -928,6 +941,7 @@ vi_status batch_enqueue_iteration(vi_batch* b, bool masked = false) {
     }
   if (parity) vi::launch_batch_copy(b->st, B, b->blk, grid, slot++);
   vi::launch_batch_recon(b->st, B, rgrid, slot++, masked);
+  vi::launch_batch_sum_abs(b->st, B, b->cap_jobs, b->d_abs);
   return launched("batched iteration");
 }
 
@@ -984,8 +998,8 @@ vi_status batch_onion(vi_batch* b, std::vector<vi_ctx*> active) {
       J.smask = c->o_S;
       J.excl = Hp[i];
       J.step = (uint64_t(1) << 32) + (uint64_t)layer;
-      J.evals = c->d_u64 + 5;
-      J.evals_init = c->d_u64 + 5;
+      J.evals = c->d_cnt + 3 * (size_t)vi::kCntWords;
+      J.evals_init = c->d_cnt + 3 * (size_t)vi::kCntWords;
       c->n_nominal += per_target_evals(c->prm, r_max(c->lv[level].d)) * (int64_t)J.nS;
       c->n_searches += 1;
       c->n_recon += J.nH;
@@ -1121,11 +1135,13 @@ vi_status vi_batch_create(vi_batch** out, const vi_tune* tune, void* hip_stream)
     b->h_abs = nullptr;
   }
   b->d_abs = static_cast<unsigned long long*>(alloc(sizeof(unsigned long long) * b->cap_jobs));
-  b->d_scratch = static_cast<unsigned long long*>(alloc(sizeof(unsigned long long) * 8));
+  b->d_scratch = static_cast<unsigned long long*>(alloc(sizeof(unsigned long long) * vi::kCntWords));
+  b->d_abs_spread = static_cast<unsigned long long*>(
+      alloc(sizeof(unsigned long long) * vi::kCntWords * (size_t)b->cap_jobs));
   b->d_queue = static_cast<int32_t*>(alloc(sizeof(int32_t) * vi::kQueueSlots));
   (void)p;
   if (!b->d_jobs || !b->d_tchunk_job || !b->d_pchunk_job || !b->d_counts || !b->d_abs ||
-      !b->d_scratch || !b->d_queue || !b->h_abs) {
+      !b->d_scratch || !b->d_queue || !b->h_abs || !b->d_abs_spread) {
     vi_batch_destroy(b);
     return fail(VI_E_NOMEM, "batch allocation failed");
   }

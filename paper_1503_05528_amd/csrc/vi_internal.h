@@ -67,7 +67,7 @@ struct PassArgs {
   int32_t rs_k;            // PatchMatch iteration of the random search, 0 = none
   int32_t R;               // random-search radius floor(r_max rho^k)
   uint64_t step;           // Philox counter word 1
-  unsigned long long* evals;  // effective-evaluation counter, or null
+  unsigned long long* evals;  // effective-evaluation counter (spread), or null
 };
 
 // One clip's EM iteration inside a batched launch (device memory).
@@ -84,7 +84,7 @@ struct JobDesc {
   const uint8_t* smask;  // target-set membership (masked launches: onion layer)
   const uint8_t* excl;   // voxels excluded from comparisons and votes (onion: H')
   uint64_t step;    // EM index at the level (Philox counter word 1)
-  unsigned long long* absdiff;
+  unsigned long long* absdiff;     // spread counters (kCntWords words each)
   unsigned long long* evals;       // distances computed by the passes
   unsigned long long* evals_init;  // distances computed by step 0
   int32_t R[kMaxPmIters + 1];  // random-search radius of iteration k
@@ -94,6 +94,15 @@ constexpr int kPixChunk = 64;  // hole pixels per chunk of a batched reconstruct
 
 constexpr int kQueueSlots = 1024;  // chunk counters, one per launch of a batched iteration
 
+// Counters that every wave adds to (evaluation counts, |change| sums) are
+// spread over kCntSlots slots, one 128-byte line each: a wave adds its sum to
+// the slot of its wave index, and a reader sums the slots.  Tens of thousands
+// of device-scope atomics on one address per launch serialise in the memory
+// system and cost more than the work they count.
+constexpr int kCntSlots = 64;
+constexpr int kCntStride = 16;  // 64-bit words per slot
+constexpr int kCntWords = kCntSlots * kCntStride;
+
 struct BatchArgs {
   const JobDesc* jobs;
   const int32_t* tchunk_job;  // job of every target chunk
@@ -102,6 +111,10 @@ struct BatchArgs {
   int32_t* queue;             // [kQueueSlots] next chunk of each persistent launch
   int32_t direct;             // 1: one workgroup per chunk (grid = chunk count)
 };
+
+// out[i] = sum of the slots of the spread counter base + i * kCntWords, i < n
+void launch_sum_spread(hipStream_t st, const unsigned long long* base, int32_t n,
+                       unsigned long long* out);
 
 // ---------------------------------------------------------------- launchers
 // All launch on `st`; none synchronises.
@@ -151,6 +164,9 @@ void launch_batch_pass(hipStream_t st, const BatchArgs& B, int blk, int32_t grid
 void launch_batch_copy(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t slot);
 void launch_batch_recon(hipStream_t st, const BatchArgs& B, int32_t grid, int32_t slot,
                         bool masked = false);
+// out[j] = |change| sum of job j (the slots of its spread counter J.absdiff)
+void launch_batch_sum_abs(hipStream_t st, const BatchArgs& B, int32_t max_jobs,
+                          unsigned long long* out);
 
 // stream compaction (stable): out[k] = i for the k-th i with flags[i] != 0
 size_t compact_temp_bytes(int32_t n);

@@ -103,82 +103,78 @@ __device__ __forceinline__ void acc_voxel(SsdAcc& q, uint2 a, uint2 b) {
 
 // rows [R0, R1) of the centre-out order; FULL: every target voxel is in the
 // volume and compared (no masks)
-template <int R0, int R1, bool FULL, bool MASKED>
-__device__ __forceinline__ void ssd_rows(const DevLevel& L, const uint8_t* __restrict__ excl,
-                                         int32_t p, int32_t px, int32_t py, int32_t pt, int32_t c,
-                                         SsdAcc& q) {
+// Five consecutive voxels (one patch row, dx = -2..2) with two 16-byte loads
+// and one 8-byte load.  The pointer is only 8-byte aligned and the type says
+// so: the compiler picks the widest loads that alignment allows.
+typedef uint32_t u32x4_a8 __attribute__((ext_vector_type(4), aligned(8)));
+
+struct Row5 {
+  uint2 v[5];
+};
+
+__device__ __forceinline__ Row5 load_row5(const uint2* __restrict__ r) {
+  const u32x4_a8 v01 = *reinterpret_cast<const u32x4_a8*>(r);
+  const u32x4_a8 v23 = *reinterpret_cast<const u32x4_a8*>(r + 2);
+  Row5 o;
+  o.v[0] = make_uint2(v01.x, v01.y);
+  o.v[1] = make_uint2(v01.z, v01.w);
+  o.v[2] = make_uint2(v23.x, v23.y);
+  o.v[3] = make_uint2(v23.z, v23.w);
+  o.v[4] = r[4];
+  return o;
+}
+
+// one row (dt, dy) of the patch pair; FULL: every target voxel is in the
+// volume and compared (no masks)
+template <bool FULL, bool MASKED>
+__device__ __forceinline__ void ssd_row(const DevLevel& L, const uint8_t* __restrict__ excl,
+                                        int32_t p, int32_t px, int32_t py, int32_t pt, int32_t c,
+                                        int dt, int dy, SsdAcc& q) {
   const uint2* __restrict__ vox = L.vox;
+  const int32_t row = dt * L.WH + dy * L.W;
+  // the candidate patch lies inside the volume: its row is one span
+  const Row5 b = load_row5(vox + (c + row - 2));
+  if (FULL) {
+    const Row5 a = load_row5(vox + (p + row - 2));
 #pragma unroll
-  for (int r = R0; r < R1; ++r) {
-    const int dt = kRowDt[r], dy = kRowDy[r];
-    const int32_t row = dt * L.WH + dy * L.W;
-    if (FULL) {
+    for (int k = 0; k < 5; ++k) acc_voxel(q, a.v[k], b.v[k]);
+  } else {
+    const int32_t tt = pt + dt, yy = py + dy;
+    const bool rok = tt >= 0 && tt < L.T && yy >= 0 && yy < L.H;
 #pragma unroll
-      for (int dx = -2; dx <= 2; ++dx) acc_voxel(q, vox[p + row + dx], vox[c + row + dx]);
-    } else {
-      const int32_t tt = pt + dt, yy = py + dy;
-      const bool rok = tt >= 0 && tt < L.T && yy >= 0 && yy < L.H;
-#pragma unroll
-      for (int dx = -2; dx <= 2; ++dx) {
-        const int32_t xx = px + dx;
-        bool ok = rok && xx >= 0 && xx < L.W;
-        const int32_t ai = ok ? p + row + dx : p;
-        if (MASKED) ok = ok && !excl[ai];
-        uint2 a = vox[ai];
-        uint2 b = vox[c + row + dx];
-        if (!ok) {
-          a = make_uint2(0, 0);
-          b = make_uint2(0, 0);
-        }
-        q.n += ok ? 1 : 0;
-        acc_voxel(q, a, b);
+    for (int dx = -2; dx <= 2; ++dx) {
+      const int32_t xx = px + dx;
+      bool ok = rok && xx >= 0 && xx < L.W;
+      const int32_t ai = ok ? p + row + dx : p;
+      if (MASKED) ok = ok && !excl[ai];
+      uint2 a = vox[ai];
+      uint2 bb = b.v[dx + 2];
+      if (!ok) {
+        a = make_uint2(0, 0);
+        bb = make_uint2(0, 0);
       }
+      q.n += ok ? 1 : 0;
+      acc_voxel(q, a, bb);
     }
   }
 }
 
+// The centre row, then twelve groups of two rows in a loop that is not
+// unrolled: the two rows of a group are fetched together, and the code stays
+// small enough for the instruction cache although the kernels inline it at
+// several call sites.
 template <bool FULL, bool MASKED, bool ABORT>
 __device__ __forceinline__ uint32_t ssd_groups(const DevLevel& L, const uint8_t* excl, int32_t p,
                                                int32_t px, int32_t py, int32_t pt, int32_t c,
                                                uint32_t abort_above, int32_t& nvox) {
   SsdAcc q{0u, 0u, 0};
   const uint32_t lam = (uint32_t)L.lambda;
-  ssd_rows<0, 1, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
-  if (!ABORT || q.sc + lam * q.st <= abort_above) {
-    ssd_rows<1, 3, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
-    if (!ABORT || q.sc + lam * q.st <= abort_above) {
-      ssd_rows<3, 5, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
-      if (!ABORT || q.sc + lam * q.st <= abort_above) {
-        ssd_rows<5, 7, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
-        if (!ABORT || q.sc + lam * q.st <= abort_above) {
-          ssd_rows<7, 9, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
-          if (!ABORT || q.sc + lam * q.st <= abort_above) {
-            ssd_rows<9, 11, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
-            if (!ABORT || q.sc + lam * q.st <= abort_above) {
-              ssd_rows<11, 13, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
-              if (!ABORT || q.sc + lam * q.st <= abort_above) {
-                ssd_rows<13, 15, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
-                if (!ABORT || q.sc + lam * q.st <= abort_above) {
-                  ssd_rows<15, 17, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
-                  if (!ABORT || q.sc + lam * q.st <= abort_above) {
-                    ssd_rows<17, 19, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
-                    if (!ABORT || q.sc + lam * q.st <= abort_above) {
-                      ssd_rows<19, 21, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
-                      if (!ABORT || q.sc + lam * q.st <= abort_above) {
-                        ssd_rows<21, 23, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
-                        if (!ABORT || q.sc + lam * q.st <= abort_above) {
-                          ssd_rows<23, 25, FULL, MASKED>(L, excl, p, px, py, pt, c, q);
-                        }
-                      }
-                    }
-                  }
-                }
-              }
-            }
-          }
-        }
-      }
-    }
+  ssd_row<FULL, MASKED>(L, excl, p, px, py, pt, c, 0, 0, q);
+#pragma unroll 1
+  for (int r = 1; r < 25; r += 2) {
+    if (ABORT && q.sc + lam * q.st > abort_above) break;
+    ssd_row<FULL, MASKED>(L, excl, p, px, py, pt, c, kRowDt[r], kRowDy[r], q);
+    ssd_row<FULL, MASKED>(L, excl, p, px, py, pt, c, kRowDt[r + 1], kRowDy[r + 1], q);
   }
   nvox = FULL ? 125 : q.n;
   return q.sc + lam * q.st;
@@ -201,10 +197,18 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
   return v;
 }
 
+// adds the wave's sum of v to the spread counter at base (every lane calls)
+__device__ __forceinline__ void add_spread(unsigned long long* base, unsigned long long v) {
+  const unsigned long long s = wave_sum_u64(v);
+  if ((threadIdx.x & 63) == 0 && s) {
+    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    atomicAdd(base + (wave & (kCntSlots - 1)) * kCntStride, s);
+  }
+}
+
 __device__ __forceinline__ void count_evals(unsigned long long* evals, int n) {
   if (!evals) return;
-  unsigned long long s = wave_sum_u64((unsigned long long)n);
-  if ((threadIdx.x & 63) == 0 && s) atomicAdd(evals, s);
+  add_spread(evals, (unsigned long long)n);
 }
 
 // ------------------------------------------------------------------------
@@ -456,8 +460,9 @@ __global__ void k_copy_targets(const int32_t* tlist, int32_t nS, const int2* src
 // double, which is exact for ordering: distinct such fractions (numerators
 // < 2^31, denominators <= 125) differ by more than the double spacing.
 // WEIGHTED: sigma^2 is the ceil(3m/4)-th smallest delta (nearest rank),
-// selected by radix walks with wave ballots (float32 keys, then exact keys
-// when a float value is shared by different deltas); weights
+// selected by a radix walk with wave ballots over the integer distances when
+// all contributors share one voxel count, else over float32 keys and then
+// the exact keys when a float value is shared by different deltas; weights
 // exp(-delta_q / (2 sigma^2)) with the ratio formed as one double division of
 // exact integer products, then float32.  BEST: (delta, offset index) argmin.
 // ------------------------------------------------------------------------
@@ -506,8 +511,9 @@ __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __
       v[k] = L.vox[src];
       dist[k] = valid[k] ? nn[k].y : 0;
       nv[k] = valid[k] ? (int32_t)nb[k] : 1;
-      const double dl = (double)dist[k] / (double)nv[k];
-      key[k] = valid[k] ? (uint64_t)__double_as_longlong(dl) : ~0ull;
+      if (MODE == 2)
+        key[k] = valid[k] ? (uint64_t)__double_as_longlong((double)dist[k] / (double)nv[k])
+                          : ~0ull;
       if (!valid[k]) v[k] = make_uint2(0, 0);
     }
     float s[2] = {0.f, 0.f};
@@ -540,73 +546,79 @@ __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __
       s[0] = valid[0] ? 1.f : 0.f;
       s[1] = valid[1] ? 1.f : 0.f;
     } else {
-      const uint64_t b0 = __ballot(valid[0]), b1 = __ballot(valid[1]);
-      const int m = __popcll(b0) + __popcll(b1);
+      // candidate sets as wave masks (slot 0 and slot 1 of every lane): the
+      // selection runs on scalar registers, one ballot per slot and bit
+      uint64_t a0 = __ballot(valid[0]), a1 = __ballot(valid[1]);
+      const int m = __popcll(a0) + __popcll(a1);
       int rr = (3 * m + 3) >> 2;  // 1-based rank
-      // (1) radix walk over the float32 rounding of delta: rounding is
-      // monotone, so the rr-th smallest float key is the rounding of the
-      // rr-th smallest delta; rr ends as the rank inside that float's group
-      uint32_t fk[2];
+      // When every valid contributor compared the same number of voxels (all
+      // pixels away from the borders of the volume and of the onion's known
+      // region), delta is ordered as the integer distance: the walk runs on
+      // the distances themselves and no tie needs an exact second look.
+      const int fs = a0 ? (int)__ffsll((unsigned long long)a0) - 1
+                        : (int)__ffsll((unsigned long long)a1) - 1;
+      const int32_t n_first = __shfl(a0 ? nv[0] : nv[1], fs);
+      const bool uni =
+          (__ballot(valid[0] && nv[0] != n_first) | __ballot(valid[1] && nv[1] != n_first)) == 0;
+      uint32_t uk[2];
+      if (uni) {
+        uk[0] = (uint32_t)dist[0];
+        uk[1] = (uint32_t)dist[1];
+      } else {
+        // float32 rounding of the exact double key: monotone, so the walk
+        // selects the float group that holds the rr-th smallest delta
 #pragma unroll
-      for (int k = 0; k < 2; ++k)
-        fk[k] = valid[k] ? __float_as_uint((float)__longlong_as_double((long long)key[k])) : 0u;
-      uint32_t fpre = 0, fmask = 0x80000000u;
+        for (int k = 0; k < 2; ++k) {
+          key[k] = valid[k] ? (uint64_t)__double_as_longlong((double)dist[k] / (double)nv[k])
+                            : ~0ull;
+          uk[k] = valid[k] ? __float_as_uint((float)__longlong_as_double((long long)key[k])) : 0u;
+        }
+      }
+      // keys are below 2^31 (distances) or non-negative floats
+#pragma unroll
       for (int b = 30; b >= 0; --b) {
-        const uint32_t bit = 1u << b;
-        const bool z0 = valid[0] && ((fk[0] & fmask) == fpre) && !(fk[0] & bit);
-        const bool z1 = valid[1] && ((fk[1] & fmask) == fpre) && !(fk[1] & bit);
-        const int cnt = __popcll(__ballot(z0)) + __popcll(__ballot(z1));
+        const uint64_t t0 = __ballot((uk[0] >> b) & 1u), t1 = __ballot((uk[1] >> b) & 1u);
+        const uint64_t z0 = a0 & ~t0, z1 = a1 & ~t1;
+        const int cnt = __popcll(z0) + __popcll(z1);
         if (rr > cnt) {
           rr -= cnt;
-          fpre |= bit;
+          a0 &= t0;
+          a1 &= t1;
+        } else {
+          a0 = z0;
+          a1 = z1;
         }
-        fmask |= bit;
       }
-      // (2) inside the group the exact keys are almost always all equal; if
-      // not, finish with a radix walk over the exact 64-bit keys of the group
-      const bool g0 = valid[0] && fk[0] == fpre;
-      const bool g1 = valid[1] && fk[1] == fpre;
-      uint64_t kmin = ~0ull, kmax = 0;
-      if (g0) {
-        kmin = key[0];
-        kmax = key[0];
-      }
-      if (g1) {
-        kmin = key[1] < kmin ? key[1] : kmin;
-        kmax = key[1] > kmax ? key[1] : kmax;
-      }
-      for (int off = 32; off >= 1; off >>= 1) {
-        const uint64_t a = __shfl_xor(kmin, off), bb = __shfl_xor(kmax, off);
-        kmin = a < kmin ? a : kmin;
-        kmax = bb > kmax ? bb : kmax;
-      }
-      uint64_t prefix = kmin;
-      if (kmin != kmax) {
-        uint64_t pre = 0, mask = 0;
-        for (int b = 63; b >= 0; --b) {
-          const uint64_t bit = 1ull << b;
-          const bool z0 = g0 && ((key[0] & mask) == pre) && !(key[0] & bit);
-          const bool z1 = g1 && ((key[1] & mask) == pre) && !(key[1] & bit);
-          const int cnt = __popcll(__ballot(z0)) + __popcll(__ballot(z1));
-          if (rr > cnt) {
-            rr -= cnt;
-            pre |= bit;
+      // (a0, a1) now holds the contributors whose key equals the selected
+      // one and rr the rank among them; float keys can merge distinct
+      // deltas, which a walk over the exact keys of the group separates
+      if (!uni) {
+        const int gl = a0 ? (int)__ffsll((unsigned long long)a0) - 1
+                          : (int)__ffsll((unsigned long long)a1) - 1;
+        const uint64_t kf = __shfl(a0 ? key[0] : key[1], gl);
+        const bool in0 = (a0 >> lane) & 1ull, in1 = (a1 >> lane) & 1ull;
+        if ((__ballot(in0 && key[0] != kf) | __ballot(in1 && key[1] != kf)) != 0) {
+          for (int b = 63; b >= 0; --b) {
+            const uint64_t t0 = __ballot((key[0] >> b) & 1ull), t1 = __ballot((key[1] >> b) & 1ull);
+            const uint64_t z0 = a0 & ~t0, z1 = a1 & ~t1;
+            const int cnt = __popcll(z0) + __popcll(z1);
+            if (rr > cnt) {
+              rr -= cnt;
+              a0 &= t0;
+              a1 &= t1;
+            } else {
+              a0 = z0;
+              a1 = z1;
+            }
           }
-          mask |= bit;
         }
-        prefix = pre;
       }
-      // a contributor holding the selected key provides (dist_r, n_r)
-      const bool h0 = valid[0] && key[0] == prefix;
-      const bool h1 = valid[1] && key[1] == prefix;
-      const uint64_t hb0 = __ballot(h0), hb1 = __ballot(h1);
-      const int src_lane = hb0 ? (__ffsll((unsigned long long)hb0) - 1)
-                               : (__ffsll((unsigned long long)hb1) - 1);
-      const int src_k = hb0 ? 0 : 1;
-      const int32_t my_d = src_k == 0 ? dist[0] : dist[1];
-      const int32_t my_n = src_k == 0 ? nv[0] : nv[1];
-      const int32_t dr = __shfl(my_d, src_lane);
-      const int32_t nr = __shfl(my_n, src_lane);
+      // a contributor holding the selected delta provides (dist_r, n_r)
+      const int src_lane = a0 ? (int)__ffsll((unsigned long long)a0) - 1
+                              : (int)__ffsll((unsigned long long)a1) - 1;
+      const int src_k = a0 ? 0 : 1;
+      const int32_t dr = __shfl(src_k == 0 ? dist[0] : dist[1], src_lane);
+      const int32_t nr = __shfl(src_k == 0 ? nv[0] : nv[1], src_lane);
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         if (!valid[k]) continue;
@@ -688,7 +700,7 @@ __global__ __launch_bounds__(kBlock) void k_recon(DevLevel L, const int32_t* __r
   unsigned long long my_abs = 0;
   for (int32_t w = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); w < nP; w += nwaves)
     recon_pixel<MODE, FILT>(L, plist, w, excl, out_f, my_abs);
-  if (absdiff && (threadIdx.x & 63) == 0 && my_abs) atomicAdd(absdiff, my_abs);
+  if (absdiff) add_spread(absdiff, (threadIdx.x & 63) == 0 ? my_abs : 0ull);
 }
 
 
@@ -737,8 +749,27 @@ __device__ __forceinline__ bool next_chunk(int32_t* counter, int32_t n, bool dir
 
 __global__ void kb_zero(BatchArgs B) {
   const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < B.counts[2]) *B.jobs[j].absdiff = 0;
+  if (j < B.counts[2] * kCntSlots)
+    B.jobs[j / kCntSlots].absdiff[(j % kCntSlots) * kCntStride] = 0;
   if (j < kQueueSlots) B.queue[j] = 0;
+}
+
+__global__ void kb_sum_abs(BatchArgs B, unsigned long long* out) {
+  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= B.counts[2]) return;
+  const unsigned long long* a = B.jobs[j].absdiff;
+  unsigned long long s = 0;
+  for (int k = 0; k < kCntSlots; ++k) s += a[k * kCntStride];
+  out[j] = s;
+}
+
+__global__ void k_sum_spread(const unsigned long long* base, int32_t n, unsigned long long* out) {
+  const int32_t i = blockIdx.x;
+  if (i >= n) return;
+  const int lane = threadIdx.x;  // one wave per counter, one slot per lane
+  unsigned long long v = base[(size_t)i * kCntWords + lane * kCntStride];
+  v = wave_sum_u64(v);
+  if (lane == 0) out[i] = v;
 }
 
 template <int BLK, bool MASKED>
@@ -816,7 +847,7 @@ __global__ __launch_bounds__(kBlock) void kb_recon(BatchArgs B, int32_t slot) {
       else
         recon_pixel<0, FILT>(L, J.hlist, w, J.excl, nullptr, my_abs);
     }
-    if ((threadIdx.x & 63) == 0 && my_abs) atomicAdd(J.absdiff, my_abs);
+    add_spread(J.absdiff, (threadIdx.x & 63) == 0 ? my_abs : 0ull);
   }
 }
 
@@ -1223,8 +1254,22 @@ hipError_t compact(hipStream_t st, const uint8_t* flags, int32_t n, int32_t* out
 namespace vi {
 
 void launch_batch_zero(hipStream_t st, const BatchArgs& B, int32_t max_jobs) {
-  const int32_t n = max_jobs > kQueueSlots ? max_jobs : kQueueSlots;
+  const int32_t nz = max_jobs * kCntSlots;
+  const int32_t n = nz > kQueueSlots ? nz : kQueueSlots;
   kb_zero<<<dim3((unsigned)((n + 255) / 256)), 256, 0, st>>>(B);
+}
+
+void launch_batch_sum_abs(hipStream_t st, const BatchArgs& B, int32_t max_jobs,
+                          unsigned long long* out) {
+  const int32_t n = max_jobs > 0 ? max_jobs : 1;
+  kb_sum_abs<<<dim3((unsigned)((n + 255) / 256)), 256, 0, st>>>(B, out);
+}
+
+void launch_sum_spread(hipStream_t st, const unsigned long long* base, int32_t n,
+                       unsigned long long* out) {
+  static_assert(kCntSlots == 64, "one lane per slot");
+  if (n <= 0) return;
+  k_sum_spread<<<dim3((unsigned)n), 64, 0, st>>>(base, n, out);
 }
 
 template <bool M>
