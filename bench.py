@@ -12,7 +12,9 @@ second over the timed steps (the nominal count of a search is |H~| x (1 + sum
 over iterations of 6 n_jf + [radius >= 1]) and does not depend on how many
 candidates an implementation skips).  The roofline object covers the
 propagation-pass kernel, timed with HIP events on the context's stream over
-the timed steps; the CPU baseline is the oracle's search at level 1 of the
+the timed steps (one event pair around the back-to-back passes of each
+search; the average launch duration is their time over their count); the
+CPU baseline is the oracle's search at level 1 of the
 same clip on the host cores.
 """
 import argparse
@@ -379,13 +381,13 @@ def main():
     ms_per_step = 1000.0 * elapsed / a.steps
 
     kinds = {}
-    for kind, lvl, units, ms in recs:
+    for kind, lvl, units, ms, nl in recs:
         d = kinds.setdefault(kind, {"launches": 0, "units": 0, "ms": 0.0})
-        d["launches"] += 1
+        d["launches"] += nl
         d["units"] += units
         d["ms"] += ms
     by_level = {}
-    for kind, lvl, units, ms in recs:
+    for kind, lvl, units, ms, nl in recs:
         key = f"{kind}@L{lvl}"
         by_level[key] = round(by_level.get(key, 0.0) + ms / a.steps, 3)
     pas = kinds.get("pass", {"launches": 1, "units": 0, "ms": 1.0})

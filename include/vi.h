@@ -230,8 +230,10 @@ typedef struct {
 vi_status vi_get_counters(vi_ctx* ctx, vi_counters* out);
 vi_status vi_reset_counters(vi_ctx* ctx);
 
-/* Kernel timing with HIP events recorded on the context's stream around
- * every launch of the hot path while profiling is on. */
+/* Kernel timing with HIP events recorded on the context's stream while
+ * profiling is on: one event pair around each launch, except the
+ * propagation passes of one search, which run back to back and share one
+ * pair (launches > 1; their average duration is ms / launches). */
 typedef enum {
   VI_K_INIT = 0,   /* search step 0; units = targets */
   VI_K_PASS = 1,   /* propagation / random-search pass; units = nominal evals */
@@ -244,6 +246,7 @@ typedef struct {
   int32_t level;
   int64_t units;
   float ms;
+  int32_t launches; /* launches the record covers */
 } vi_kernel_time;
 vi_status vi_profile(vi_ctx* ctx, int32_t on);
 /* Copies up to cap records (host) of the launches timed since the last read

@@ -78,6 +78,7 @@ struct vi_ctx {
     int32_t kind, level;
     int64_t units;
     int ev;
+    int32_t launches;
   };
   std::vector<hipEvent_t> events;  // pairs (start, stop)
   std::vector<Rec> recs;
@@ -138,16 +139,18 @@ int prof_begin(vi_ctx* c) {
   }
   const int ev = (int)(2 * c->recs.size());
   if (hipEventRecord(c->events[ev], c->st) != hipSuccess) return -1;
-  c->recs.push_back({0, 0, 0, ev});
+  c->recs.push_back({0, 0, 0, ev, 0});
   return (int)c->recs.size() - 1;
 }
 
-void prof_end(vi_ctx* c, int r, int32_t kind, int32_t level, int64_t units) {
+void prof_end(vi_ctx* c, int r, int32_t kind, int32_t level, int64_t units,
+              int32_t launches = 1) {
   if (r < 0) return;
   vi_ctx::Rec& rec = c->recs[(size_t)r];
   rec.kind = c->kind_override >= 0 ? c->kind_override : kind;
   rec.level = level;
   rec.units = units;
+  rec.launches = launches;
   (void)hipEventRecord(c->events[(size_t)rec.ev + 1], c->st);
 }
 
@@ -256,6 +259,10 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
   VI_TRY(launched("s0"));
   int2* buf[2] = {d.nnf0, d.nnf1};
   int cur = 0;
+  // the passes run back to back: one event pair covers all of them
+  r = prof_begin(c);
+  int64_t pass_units = 0;
+  int32_t n_pass = 0;
   for (int k = 1; k <= c->prm.pm_iters; ++k) {
     const int32_t R = rs_radius(c->prm, rmax, k);
     const bool rs = R >= 1;
@@ -267,14 +274,17 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
       A.s = c->prm.n_jf > 0 ? c->prm.jf_steps[js] : 0;
       A.rs_k = (js == np - 1 && rs) ? k : 0;
       A.R = R;
-      r = prof_begin(c);
       vi::launch_pass(c->st, d, A);
-      prof_end(c, r, VI_K_PASS, level,
-               (int64_t)nS * ((A.s > 0 ? 6 : 0) + (A.rs_k > 0 ? 1 : 0)));
+      pass_units += (int64_t)nS * ((A.s > 0 ? 6 : 0) + (A.rs_k > 0 ? 1 : 0));
+      ++n_pass;
       VI_TRY(launched("pass"));
       cur ^= 1;
     }
   }
+  if (n_pass > 0)
+    prof_end(c, r, VI_K_PASS, level, pass_units, n_pass);
+  else if (r >= 0)
+    c->recs.pop_back();
   if (cur == 1) {
     r = prof_begin(c);
     vi::launch_copy_targets(c->st, tlist, nS, d.nnf1, d.nnf0);
@@ -718,6 +728,7 @@ int32_t vi_profile_read(vi_ctx* c, vi_kernel_time* out, int32_t cap) {
     out[i].level = r.level;
     out[i].units = r.units;
     out[i].ms = ms;
+    out[i].launches = r.launches;
   }
   c->recs.clear();
   return n;

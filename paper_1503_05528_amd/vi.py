@@ -94,7 +94,7 @@ class Counters(C.Structure):
 
 class KernelTime(C.Structure):
     _fields_ = [("kind", C.c_int32), ("level", C.c_int32), ("units", C.c_int64),
-                ("ms", C.c_float)]
+                ("ms", C.c_float), ("launches", C.c_int32)]
 
 
 KERNEL_KINDS = {0: "init", 1: "pass", 2: "recon", 3: "other", 4: "onion"}
@@ -308,8 +308,8 @@ class Clip:
         n = lib().vi_profile_read(self.h, buf, cap)
         if n < 0:
             _check("vi_profile_read", n)
-        return [(KERNEL_KINDS[buf[i].kind], buf[i].level, int(buf[i].units), float(buf[i].ms))
-                for i in range(n)]
+        return [(KERNEL_KINDS[buf[i].kind], buf[i].level, int(buf[i].units), float(buf[i].ms),
+                 int(buf[i].launches)) for i in range(n)]
 
 
 class Batch:
