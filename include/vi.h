@@ -153,6 +153,13 @@ size_t vi_footprint_bytes(const vi_params* prm, int32_t W, int32_t H, int32_t T,
 /* Device bytes this context holds. */
 size_t vi_ctx_bytes(const vi_ctx* ctx);
 
+/* Device memory released by destroyed contexts is kept by the library, per
+ * device and size class, for the next vi_create (at most VI_POOL_BYTES bytes
+ * per device, environment variable, default 8 GiB); a failed allocation
+ * first gives the cache back and retries.  vi_pool_trim frees the cached
+ * memory of the current device and returns the bytes freed. */
+size_t vi_pool_trim(void);
+
 /* Rebinds the context to another stream (hipStream_t or NULL). */
 vi_status vi_set_stream(vi_ctx* ctx, void* hip_stream);
 

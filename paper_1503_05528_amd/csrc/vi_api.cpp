@@ -56,7 +56,8 @@ struct vi_ctx {
   int32_t W = 0, H = 0, T = 0;
   hipStream_t st = nullptr;
   Level lv[kMaxLevels];
-  std::vector<void*> allocs;
+  int dev = 0;                                   // device of the context
+  std::vector<std::pair<void*, size_t>> allocs;  // pooled blocks, requested sizes
   size_t bytes = 0;
   void* ctemp = nullptr;  // compaction scratch
   size_t ctemp_bytes = 0;
@@ -93,13 +94,10 @@ namespace {
 
 template <typename T>
 vi_status dalloc(vi_ctx* c, T** p, size_t n) {
-  void* q = nullptr;
   const size_t b = n * sizeof(T) > 0 ? n * sizeof(T) : 16;
-  if (hipMalloc(&q, b) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(VI_E_NOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
-  }
-  c->allocs.push_back(q);
+  void* q = vi::pool_alloc(c->dev, b);
+  if (!q) return fail(VI_E_NOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
+  c->allocs.push_back({q, b});
   c->bytes += b;
   *p = static_cast<T*>(q);
   return VI_OK;
@@ -108,11 +106,9 @@ vi_status dalloc(vi_ctx* c, T** p, size_t n) {
 void dfree(vi_ctx* c, void* p) {
   if (!p) return;
   for (size_t i = 0; i < c->allocs.size(); ++i)
-    if (c->allocs[i] == p) {
-      size_t sz = 0;
-      (void)hipMemPtrGetInfo(p, &sz);
-      c->bytes -= sz;
-      (void)hipFree(p);
+    if (c->allocs[i].first == p) {
+      c->bytes -= c->allocs[i].second;
+      vi::pool_free(c->dev, p);
       c->allocs.erase(c->allocs.begin() + (long)i);
       return;
     }
@@ -130,11 +126,8 @@ int prof_begin(vi_ctx* c) {
   if (!c->profiling) return -1;
   const size_t need = 2 * (c->recs.size() + 1);
   while (c->events.size() < need) {
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) {
-      (void)hipGetLastError();
-      return -1;
-    }
+    hipEvent_t e = vi::event_get(c->dev);
+    if (!e) return -1;
     c->events.push_back(e);
   }
   const int ev = (int)(2 * c->recs.size());
@@ -466,6 +459,10 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
   if (!video_rgb || !mask) return fail(VI_E_INVAL, "null input pointer");
   vi_ctx* c = new (std::nothrow) vi_ctx();
   if (!c) return fail(VI_E_NOMEM, "host allocation failed");
+  if (hipGetDevice(&c->dev) != hipSuccess) {
+    delete c;
+    return fail(VI_E_HIP, "no current device");
+  }
   c->prm = *prm;
   c->L = prm->levels;
   c->W = W;
@@ -551,9 +548,10 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
 
 void vi_destroy(vi_ctx* c) {
   if (!c) return;
+  // nothing queued uses the blocks after this: they may serve any stream
   (void)hipStreamSynchronize(c->st);
-  for (void* p : c->allocs) (void)hipFree(p);
-  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  for (const auto& a : c->allocs) vi::pool_free(c->dev, a.first);
+  for (hipEvent_t e : c->events) vi::event_put(c->dev, e);
   delete c;
 }
 

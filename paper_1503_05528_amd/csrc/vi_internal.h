@@ -168,6 +168,15 @@ void launch_batch_recon(hipStream_t st, const BatchArgs& B, int32_t grid, int32_
 void launch_batch_sum_abs(hipStream_t st, const BatchArgs& B, int32_t max_jobs,
                           unsigned long long* out);
 
+// Device memory and timing events reused across contexts (vi_pool.cpp).
+// pool_alloc: a block of at least `bytes` on device `dev`, or nullptr;
+// pool_free: returns a block that no queued work uses any more.
+void* pool_alloc(int dev, size_t bytes);
+void pool_free(int dev, void* p);
+size_t pool_trim(int dev);
+hipEvent_t event_get(int dev);
+void event_put(int dev, hipEvent_t e);
+
 // stream compaction (stable): out[k] = i for the k-th i with flags[i] != 0
 size_t compact_temp_bytes(int32_t n);
 hipError_t compact(hipStream_t st, const uint8_t* flags, int32_t n, int32_t* out,

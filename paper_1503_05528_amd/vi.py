@@ -61,6 +61,7 @@ SIGNATURES = {
     "vi_set_state": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp]),
     "vi_footprint_bytes": (C.c_size_t, [C.c_void_p, _i32, _i32, _i32, _f64]),
     "vi_ctx_bytes": (C.c_size_t, [_vp]),
+    "vi_pool_trim": (C.c_size_t, []),
     "vi_set_stream": (_i32, [_vp, _vp]),
     "vi_destroy": (None, [_vp]),
     "vi_last_error": (C.c_char_p, []),
@@ -153,6 +154,12 @@ def _stream_handle(stream):
 
 def footprint_bytes(params: Params, W, H, T, hole_fraction) -> int:
     return int(lib().vi_footprint_bytes(C.byref(params), W, H, T, float(hole_fraction)))
+
+
+def pool_trim() -> int:
+    """Frees the device memory libvi keeps from destroyed contexts (current
+    device); returns the bytes freed."""
+    return int(lib().vi_pool_trim())
 
 
 class Clip:
