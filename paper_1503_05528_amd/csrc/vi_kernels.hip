@@ -574,9 +574,13 @@ __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __
           uk[k] = valid[k] ? __float_as_uint((float)__longlong_as_double((long long)key[k])) : 0u;
         }
       }
-      // keys are below 2^31 (distances) or non-negative floats
+      // keys are below 2^31 (distances) or non-negative floats; the walk
+      // starts at the highest bit any key has set
+      uint32_t any = (valid[0] ? uk[0] : 0u) | (valid[1] ? uk[1] : 0u);
 #pragma unroll
-      for (int b = 30; b >= 0; --b) {
+      for (int o = 32; o >= 1; o >>= 1) any |= (uint32_t)__shfl_xor((int)any, o);
+      const int top = any ? 31 - __builtin_clz(any) : -1;
+      for (int b = top; b >= 0; --b) {
         const uint64_t t0 = __ballot((uk[0] >> b) & 1u), t1 = __ballot((uk[1] >> b) & 1u);
         const uint64_t z0 = a0 & ~t0, z1 = a1 & ~t1;
         const int cnt = __popcll(z0) + __popcll(z1);
