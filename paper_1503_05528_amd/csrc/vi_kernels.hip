@@ -592,9 +592,12 @@ __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __
           a0 = z0;
           a1 = z1;
         }
+        // one candidate left: it is the selected one
+        if (__popcll(a0) + __popcll(a1) == 1) break;
       }
       // (a0, a1) now holds the contributors whose key equals the selected
-      // one and rr the rank among them; float keys can merge distinct
+      // one (or the one contributor left) and rr the rank among them; float
+      // keys can merge distinct
       // deltas, which a walk over the exact keys of the group separates
       if (!uni) {
         const int gl = a0 ? (int)__ffsll((unsigned long long)a0) - 1
