@@ -151,8 +151,9 @@ void launch_set_state(hipStream_t st, DevLevel L, const uint8_t* rgbt, const int
 void launch_out_rgb(hipStream_t st, DevLevel L0, uint8_t* out);
 
 // batched launches over every job's chunks: persistent (grid = `grid`
-// workgroups taking chunks from a counter) or direct (B.direct, grid = the
-// chunk count); blk = targets per workgroup, 64, 128 or 256
+// workgroups taking chunks from a counter) or direct (B.direct: grid must be
+// the chunk count; the pass kernel then takes exactly one chunk per
+// workgroup); blk = targets per workgroup, 64, 128 or 256
 // `slot` selects the chunk counter of the launch; launch_batch_zero clears
 // the counters and the per-job outputs at the start of an iteration
 void launch_batch_zero(hipStream_t st, const BatchArgs& B, int32_t max_jobs);

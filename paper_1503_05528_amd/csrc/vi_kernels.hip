@@ -745,7 +745,8 @@ __device__ __forceinline__ bool next_chunk(int32_t* counter, int32_t n, bool dir
   __syncthreads();  // every thread has read the previous chunk index
   if (threadIdx.x == 0) *s_c = atomicAdd(counter, 1);
   __syncthreads();
-  cur.c = *s_c;
+  // the same value in every lane: scalar registers address the job
+  cur.c = __builtin_amdgcn_readfirstlane(*s_c);
   return cur.c < n;
 }
 
@@ -779,48 +780,74 @@ __global__ void k_sum_spread(const unsigned long long* base, int32_t n, unsigned
   if (lane == 0) out[i] = v;
 }
 
+// A field of the job descriptor, read word by word into scalar registers:
+// the job index is the same in every lane, but the compiler cannot prove that
+// the table is not written during the kernel and would otherwise keep the
+// descriptor in vector registers.
+template <typename T>
+__device__ __forceinline__ T uniform(const T& src) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized fields");
+  uint32_t w[sizeof(T) / 4];
+  __builtin_memcpy(w, &src, sizeof(T));
+#pragma unroll
+  for (size_t i = 0; i < sizeof(T) / 4; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  T out;
+  __builtin_memcpy(&out, w, sizeof(T));
+  return out;
+}
+
 template <int BLK, bool MASKED>
 __global__ __launch_bounds__(BLK) void kb_s0(BatchArgs B, int32_t slot) {
   const int32_t n = B.counts[0];
   FOR_EACH_CHUNK(B.queue + slot, n, B.direct, c) {
-    // a private copy: the descriptor stays in scalar registers in the hot loops
-    const JobDesc& Jg = B.jobs[B.tchunk_job[c]];
-    const DevLevel L = Jg.L;
-    const JobDesc& J = Jg;
+    const JobDesc& J = B.jobs[__builtin_amdgcn_readfirstlane(B.tchunk_job[c])];
+    const DevLevel L = uniform(J.L);
     PassArgs A{};
-    A.tlist = J.tlist;
-    A.nS = J.nS;
-    A.excl = J.excl;
+    A.tlist = uniform(J.tlist);
+    A.nS = uniform(J.nS);
+    A.excl = uniform(J.excl);
     A.nin = L.nnf0;
-    A.step = J.step;
-    const int ne = s0_target<MASKED>(L, A, (c - J.tchunk0) * BLK + (int32_t)threadIdx.x);
-    count_evals(J.evals_init, ne);
+    A.step = uniform(J.step);
+    const int ne = s0_target<MASKED>(L, A, (c - uniform(J.tchunk0)) * BLK + (int32_t)threadIdx.x);
+    count_evals(uniform(J.evals_init), ne);
   }
 }
 
+// one chunk of a batched pass (every thread of the workgroup calls it)
 template <int BLK, bool MASKED>
+__device__ __forceinline__ void kb_pass_chunk(const BatchArgs& B, PassShared<BLK>& sh, int32_t c,
+                                              int32_t s, int32_t k, int32_t parity) {
+  const JobDesc& J = B.jobs[__builtin_amdgcn_readfirstlane(B.tchunk_job[c])];
+  const DevLevel L = uniform(J.L);
+  PassArgs A{};
+  A.tlist = uniform(J.tlist);
+  A.nS = uniform(J.nS);
+  A.smask = MASKED ? uniform(J.smask) : L.htil;
+  A.excl = uniform(J.excl);
+  A.nin = parity ? L.nnf1 : L.nnf0;
+  A.nout = parity ? L.nnf0 : L.nnf1;
+  A.s = s;
+  A.R = uniform(J.R[k]);
+  A.rs_k = (k > 0 && A.R >= 1) ? k : 0;
+  A.step = uniform(J.step);
+  const int ne = pass_block<BLK, MASKED>(L, A, c - uniform(J.tchunk0), sh);
+  count_evals(uniform(J.evals), ne);
+}
+
+// PERSIST: workgroups take chunks from the launch's counter.  Otherwise
+// (direct launches, grid = the chunk count) workgroup b takes chunk
+// xcd_block(b) and nothing else: without a loop around the pass the kernel
+// keeps the register count, and so the occupancy, of the single-clip pass.
+template <int BLK, bool MASKED, bool PERSIST>
 __global__ __launch_bounds__(BLK) void kb_pass(BatchArgs B, int32_t s, int32_t k, int32_t parity,
                                                int32_t slot) {
   __shared__ PassShared<BLK> sh;
   const int32_t n = B.counts[0];
-  FOR_EACH_CHUNK(B.queue + slot, n, B.direct, c) {
-    // a private copy: the descriptor stays in scalar registers in the hot loops
-    const JobDesc& Jg = B.jobs[B.tchunk_job[c]];
-    const DevLevel L = Jg.L;
-    const JobDesc& J = Jg;
-    PassArgs A{};
-    A.tlist = J.tlist;
-    A.nS = J.nS;
-    A.smask = MASKED ? J.smask : L.htil;
-    A.excl = J.excl;
-    A.nin = parity ? L.nnf1 : L.nnf0;
-    A.nout = parity ? L.nnf0 : L.nnf1;
-    A.s = s;
-    A.R = J.R[k];
-    A.rs_k = (k > 0 && A.R >= 1) ? k : 0;
-    A.step = J.step;
-    const int ne = pass_block<BLK, MASKED>(L, A, c - J.tchunk0, sh);
-    count_evals(J.evals, ne);
+  if (PERSIST) {
+    FOR_EACH_CHUNK(B.queue + slot, n, false, c) kb_pass_chunk<BLK, MASKED>(B, sh, c, s, k, parity);
+  } else {
+    const int32_t c = xcd_block(blockIdx.x, gridDim.x);
+    if (c < n) kb_pass_chunk<BLK, MASKED>(B, sh, c, s, k, parity);
   }
 }
 
@@ -828,12 +855,11 @@ template <int BLK>
 __global__ __launch_bounds__(BLK) void kb_copy(BatchArgs B, int32_t slot) {
   const int32_t n = B.counts[0];
   FOR_EACH_CHUNK(B.queue + slot, n, B.direct, c) {
-    // a private copy: the descriptor stays in scalar registers in the hot loops
-    const JobDesc& Jg = B.jobs[B.tchunk_job[c]];
-    const DevLevel L = Jg.L;
-    const JobDesc& J = Jg;
-    const int32_t i = (c - J.tchunk0) * BLK + (int32_t)threadIdx.x;
-    if (i < J.nS) L.nnf0[J.tlist[i]] = L.nnf1[J.tlist[i]];
+    const JobDesc& J = B.jobs[__builtin_amdgcn_readfirstlane(B.tchunk_job[c])];
+    const DevLevel L = uniform(J.L);
+    const int32_t* tlist = uniform(J.tlist);
+    const int32_t i = (c - uniform(J.tchunk0)) * BLK + (int32_t)threadIdx.x;
+    if (i < uniform(J.nS)) L.nnf0[tlist[i]] = L.nnf1[tlist[i]];
   }
 }
 
@@ -842,19 +868,21 @@ __global__ __launch_bounds__(kBlock) void kb_recon(BatchArgs B, int32_t slot) {
   constexpr int kWaves = kBlock / 64;
   const int32_t n = B.counts[1];
   FOR_EACH_CHUNK(B.queue + slot, n, B.direct, c) {
-    const JobDesc& Jg = B.jobs[B.pchunk_job[c]];
-    const DevLevel L = Jg.L;
-    const JobDesc& J = Jg;
-    const int32_t base = (c - J.pchunk0) * kPixChunk;
-    const int32_t end = min(J.nH, base + kPixChunk);
+    const JobDesc& J = B.jobs[__builtin_amdgcn_readfirstlane(B.pchunk_job[c])];
+    const DevLevel L = uniform(J.L);
+    const int32_t* hlist = uniform(J.hlist);
+    const uint8_t* excl = uniform(J.excl);
+    const int32_t base = (c - uniform(J.pchunk0)) * kPixChunk;
+    const int32_t end = min(uniform(J.nH), base + kPixChunk);
+    const int32_t mode = uniform(J.recon_mode);
     unsigned long long my_abs = 0;
     for (int32_t w = base + (int32_t)(threadIdx.x >> 6); w < end; w += kWaves) {
-      if (J.recon_mode == 1)
-        recon_pixel<1, FILT>(L, J.hlist, w, J.excl, nullptr, my_abs);
+      if (mode == 1)
+        recon_pixel<1, FILT>(L, hlist, w, excl, nullptr, my_abs);
       else
-        recon_pixel<0, FILT>(L, J.hlist, w, J.excl, nullptr, my_abs);
+        recon_pixel<0, FILT>(L, hlist, w, excl, nullptr, my_abs);
     }
-    add_spread(J.absdiff, (threadIdx.x & 63) == 0 ? my_abs : 0ull);
+    add_spread(uniform(J.absdiff), (threadIdx.x & 63) == 0 ? my_abs : 0ull);
   }
 }
 
@@ -1297,15 +1325,24 @@ void launch_batch_s0(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, 
     batch_s0<false>(st, B, blk, grid, slot);
 }
 
+template <bool M, bool P>
+static void batch_pass_shape(hipStream_t st, const BatchArgs& B, int blk, int32_t grid,
+                             int32_t s, int32_t k, int32_t parity, int32_t slot) {
+  if (blk == 64)
+    kb_pass<64, M, P><<<grid, 64, 0, st>>>(B, s, k, parity, slot);
+  else if (blk == 128)
+    kb_pass<128, M, P><<<grid, 128, 0, st>>>(B, s, k, parity, slot);
+  else
+    kb_pass<256, M, P><<<grid, 256, 0, st>>>(B, s, k, parity, slot);
+}
+
 template <bool M>
 static void batch_pass(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t s,
                        int32_t k, int32_t parity, int32_t slot) {
-  if (blk == 64)
-    kb_pass<64, M><<<grid, 64, 0, st>>>(B, s, k, parity, slot);
-  else if (blk == 128)
-    kb_pass<128, M><<<grid, 128, 0, st>>>(B, s, k, parity, slot);
+  if (B.direct)
+    batch_pass_shape<M, false>(st, B, blk, grid, s, k, parity, slot);
   else
-    kb_pass<256, M><<<grid, 256, 0, st>>>(B, s, k, parity, slot);
+    batch_pass_shape<M, true>(st, B, blk, grid, s, k, parity, slot);
 }
 
 void launch_batch_pass(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t s,
