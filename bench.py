@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-level", type=int, default=1)
     ap.add_argument("--cpu-searches", type=int, default=3)
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="time the oracle on one host core and on all of them and exit")
+    ap.add_argument("--oracle-timing-run", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-batched", action="store_true")
@@ -320,8 +323,67 @@ def cpu_baseline(clip, levels, em_iters, level, searches):
                       f"clip ({W}x{H}x{T}, {nS} targets, {evals} nominal evals, {dt:.1f} s)"}
 
 
+def oracle_timing_run():
+    """One process's oracle timings (its OpenMP thread count comes from the
+    environment): an ANN search at SD level 1, a weighted reconstruction of
+    every SD level-0 hole pixel from a fixed valid shift map, a complete
+    inpainting of the tiny clip."""
+    import numpy as np
+    from oracle import vio
+    from paper_1503_05528_amd import synth
+    out = {"threads": vio.num_threads()}
+    sd = synth.sd()
+    o = vio.Oracle(sd.occluded_input(), sd.mask, levels=4, em_tol=-1.0, em_max_iters=20, seed=1)
+    (_, _, _), (_, nS1, _) = o.info(1)
+    t0 = time.perf_counter()
+    o.nnf_search(1, 0)
+    out["sd_l1_search_s"] = time.perf_counter() - t0
+    out["sd_l1_targets"] = nS1
+    hole, dsrc, htil = o.sets(0)
+    rgbt, cand, dist, nvox = o.get_state(0)
+    rng = np.random.default_rng(5)
+    tg = np.flatnonzero(htil.ravel())
+    cand = cand.ravel().copy()
+    cand[tg] = rng.choice(np.flatnonzero(dsrc.ravel()), len(tg))
+    dist = dist.ravel().copy()
+    dist[tg] = rng.integers(0, 1 << 20, len(tg))
+    nv = nvox.ravel().copy()
+    nv[tg] = 125
+    o.set_state(0, rgbt=rgbt, cand=cand.reshape(htil.shape), dist=dist.reshape(htil.shape),
+                nvox=nv.reshape(htil.shape))
+    t0 = time.perf_counter()
+    o.reconstruct(0, vio.WEIGHTED)
+    out["sd_l0_reconstruct_s"] = time.perf_counter() - t0
+    out["sd_l0_hole_pixels"] = int(hole.sum())
+    o.close()
+    tiny = synth.tiny()
+    o = vio.Oracle(tiny.occluded_input(), tiny.mask, levels=1, em_tol=-1.0, em_max_iters=10, seed=1)
+    t0 = time.perf_counter()
+    o.inpaint()
+    out["tiny_inpaint_s"] = time.perf_counter() - t0
+    o.close()
+    print(json.dumps(out), flush=True)
+
+
+def oracle_timing():
+    import subprocess
+    res = []
+    for n in (1, os.cpu_count() or 1):
+        env = dict(os.environ, OMP_NUM_THREADS=str(n))
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-timing-run"],
+                           env=env, capture_output=True, text=True, check=True)
+        res.append(json.loads(r.stdout.strip().splitlines()[-1]))
+    print(json.dumps({"oracle_timing": res}), flush=True)
+
+
 def main():
     a = parse()
+    if a.oracle_timing_run:
+        oracle_timing_run()
+        return
+    if a.oracle_timing:
+        oracle_timing()
+        return
     if a.summarize_counters:
         print(json.dumps(summarize_counters(a.summarize_counters), indent=1))
         return
