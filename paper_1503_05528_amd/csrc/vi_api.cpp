@@ -256,6 +256,7 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
   r = prof_begin(c);
   int64_t pass_units = 0;
   int32_t n_pass = 0;
+  int32_t t = 0;
   for (int k = 1; k <= c->prm.pm_iters; ++k) {
     const int32_t R = rs_radius(c->prm, rmax, k);
     const bool rs = R >= 1;
@@ -267,6 +268,11 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
       A.s = c->prm.n_jf > 0 ? c->prm.jf_steps[js] : 0;
       A.rs_k = (js == np - 1 && rs) ? k : 0;
       A.R = R;
+      // passes are numbered from 1 within the search; a target may keep its
+      // match without evaluating when nothing around it changed since the
+      // previous pass at the same stride (unmasked searches only)
+      A.t = ++t;
+      A.since = (!excl && c->prm.n_jf > 0 && t > np) ? t - np : 0;
       vi::launch_pass(c->st, d, A);
       pass_units += (int64_t)nS * ((A.s > 0 ? 6 : 0) + (A.rs_k > 0 ? 1 : 0));
       ++n_pass;
@@ -436,8 +442,8 @@ size_t vi_footprint_bytes(const vi_params* prm, int32_t W, int32_t H, int32_t T,
   const int64_t V0 = (int64_t)W * H * T;
   for (int l = 0; l < prm->levels; ++l) {
     const int64_t V = w * h * T;
-    // vox 8, hole/dsrc/htil 3, nnf 16, nvox 1, source list 4
-    total += (size_t)V * 32;
+    // vox 8, hole/dsrc/htil 3, nnf 16, nvox 1, change marks 2, source list 4
+    total += (size_t)V * 34;
     // target and hole lists: the dilated hole is at most 125x the hole
     const double fr = hole_fraction * 125.0 < 1.0 ? hole_fraction * 125.0 : 1.0;
     total += (size_t)((double)V * (fr + hole_fraction) * 4.0) + 4096;
@@ -492,8 +498,11 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
     if ((st = dalloc(c, &d.vox, V)) || (st = dalloc(c, &d.hole, V)) ||
         (st = dalloc(c, &d.dsrc, V)) || (st = dalloc(c, &d.htil, V)) ||
         (st = dalloc(c, &d.nnf0, V)) ||
-        (st = dalloc(c, &d.nnf1, V)) || (st = dalloc(c, &d.nvox, V)))
+        (st = dalloc(c, &d.nnf1, V)) || (st = dalloc(c, &d.nvox, V)) ||
+        (st = dalloc(c, &d.chg, V)))
       return bail(st);
+    if (hipMemsetAsync(d.chg, 0, sizeof(uint16_t) * (size_t)V, c->st) != hipSuccess)
+      return bail(fail(VI_E_HIP, "clearing the change marks failed"));
     w = (w + 1) / 2;
     h = (h + 1) / 2;
   }
@@ -942,10 +951,14 @@ vi_status batch_enqueue_iteration(vi_batch* b, bool masked = false) {
   vi::launch_batch_zero(b->st, B, b->cap_jobs);
   vi::launch_batch_s0(b->st, B, b->blk, grid, slot++, masked);
   int parity = 0;
+  int32_t t = 0;
+  const int32_t njf = b->sched.n_jf;
   for (int k = 1; k <= b->sched.pm_iters; ++k)
-    for (int js = 0; js < b->sched.n_jf; ++js) {
+    for (int js = 0; js < njf; ++js) {
+      ++t;
       vi::launch_batch_pass(b->st, B, b->blk, grid, b->sched.jf_steps[js],
-                            js == b->sched.n_jf - 1 ? k : 0, parity, slot++, masked);
+                            js == njf - 1 ? k : 0, parity, slot++, t,
+                            (!masked && t > njf) ? t - njf : 0, masked);
       parity ^= 1;
     }
   if (parity) vi::launch_batch_copy(b->st, B, b->blk, grid, slot++);
@@ -1057,10 +1070,10 @@ vi_status batch_autotune(vi_batch* b) {
       const int32_t grid = Bm.direct ? (int32_t)b->h_tj.size() : b->ncu * kMult[im];
       const int32_t s = b->sched.n_jf > 0 ? b->sched.jf_steps[0] : 1;
       if (grid <= 0) continue;
-      vi::launch_batch_pass(b->st, Bm, kBlk[ib], grid, s, 1, 0, 1 + 4 * im);
+      vi::launch_batch_pass(b->st, Bm, kBlk[ib], grid, s, 1, 0, 1 + 4 * im, 1, 0);
       (void)hipEventRecord(e0, b->st);
       for (int r = 0; r < 3; ++r)
-        vi::launch_batch_pass(b->st, Bm, kBlk[ib], grid, s, 1, 0, 2 + 4 * im + r);
+        vi::launch_batch_pass(b->st, Bm, kBlk[ib], grid, s, 1, 0, 2 + 4 * im + r, 1, 0);
       (void)hipEventRecord(e1, b->st);
       if ((st = launched("autotune")) != VI_OK) break;
       if (hipEventSynchronize(e1) != hipSuccess) {

@@ -12,6 +12,8 @@
 //   nnf0/1 int2 [V]   (cand, dist) double buffer of the Jacobi passes; entries
 //                     outside the current target set are never read
 //   nvox   u8 [V]     number of voxels the stored distance compared
+//   chg    u16 [V]    pass of the current search that last changed the match
+//                     (0 after step 0; 0 outside the target set)
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -51,6 +53,7 @@ struct DevLevel {
   int2* nnf0;
   int2* nnf1;
   uint8_t* nvox;
+  uint16_t* chg;
   int32_t lambda;
   uint64_t seed;
 };
@@ -66,6 +69,8 @@ struct PassArgs {
   int32_t s;               // propagation stride, 0 = no propagation
   int32_t rs_k;            // PatchMatch iteration of the random search, 0 = none
   int32_t R;               // random-search radius floor(r_max rho^k)
+  int32_t t;               // index of the pass in the search, from 1
+  int32_t since;           // previous pass at the same stride, or 0: no skipping
   uint64_t step;           // Philox counter word 1
   unsigned long long* evals;  // effective-evaluation counter (spread), or null
 };
@@ -160,8 +165,11 @@ void launch_batch_zero(hipStream_t st, const BatchArgs& B, int32_t max_jobs);
 // masked: the onion peel's partial distance (J.excl) and target sets (J.smask)
 void launch_batch_s0(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t slot,
                      bool masked = false);
+// t: index of the pass in the search (from 1); since: t - n_jf when a
+// previous pass at the same stride exists, else 0 (no skipping)
 void launch_batch_pass(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t s,
-                       int32_t k, int32_t parity, int32_t slot, bool masked = false);
+                       int32_t k, int32_t parity, int32_t slot, int32_t t, int32_t since,
+                       bool masked = false);
 void launch_batch_copy(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t slot);
 void launch_batch_recon(hipStream_t st, const BatchArgs& B, int32_t grid, int32_t slot,
                         bool masked = false);

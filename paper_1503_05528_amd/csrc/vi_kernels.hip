@@ -233,6 +233,7 @@ __device__ __forceinline__ int s0_target(const DevLevel& L, const PassArgs& A, i
   const uint32_t d = patch_ssd<MASKED, false>(L, A.excl, p, px, py, pt, c, 0xffffffffu, n);
   nnf[p] = make_int2(c, (int32_t)d);
   L.nvox[p] = (uint8_t)n;
+  L.chg[p] = 0;
   return 1;
 }
 
@@ -344,6 +345,20 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
     int32_t cq[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) cq[j] = A.nin[qi[j]].x;
+    // Within a search the video is fixed, so distances are.  A target whose
+    // match is unchanged since its previous pass at this stride, and whose
+    // six neighbours' matches are unchanged since before that pass, sees
+    // exactly the candidates that lost to its match then: it keeps it.  A
+    // neighbour's entry read while it is being rewritten only holds this
+    // pass (no skip).  Entries outside the target set are never written.
+    bool stable = !MASKED && A.since > 0 && active && L.chg[p] <= A.since;
+    if (!MASKED && A.since > 0) {
+      uint16_t cg[6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) cg[j] = L.chg[qi[j]];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) stable = stable && cg[j] < A.since;
+    }
     if (MASKED) {
 #pragma unroll
       for (int j = 0; j < 6; ++j) qok[j] = qok[j] && A.smask[qi[j]] != 0;
@@ -364,7 +379,7 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
     for (int j = 0; j < 6; ++j) ds[j] = L.dsrc[qok[j] ? c[j] : 0];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      bool ok = qok[j] && ds[j] && c[j] != inc.x;
+      bool ok = !stable && qok[j] && ds[j] && c[j] != inc.x;
 #pragma unroll
       for (int k = 0; k < 6; ++k)
         if (k < j) ok = ok && !(v[k] && c[k] == c[j]);
@@ -434,6 +449,7 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
       ne += nr;
     }
     A.nout[p] = make_int2(best_c, (int32_t)best_d);
+    if (best_c != inc.x) L.chg[p] = (uint16_t)A.t;
   }
   return ne;
 }
@@ -816,7 +832,8 @@ __global__ __launch_bounds__(BLK) void kb_s0(BatchArgs B, int32_t slot) {
 // one chunk of a batched pass (every thread of the workgroup calls it)
 template <int BLK, bool MASKED>
 __device__ __forceinline__ void kb_pass_chunk(const BatchArgs& B, PassShared<BLK>& sh, int32_t c,
-                                              int32_t s, int32_t k, int32_t parity) {
+                                              int32_t s, int32_t k, int32_t parity, int32_t t,
+                                              int32_t since) {
   const JobDesc& J = B.jobs[__builtin_amdgcn_readfirstlane(B.tchunk_job[c])];
   const DevLevel L = uniform(J.L);
   PassArgs A{};
@@ -829,6 +846,8 @@ __device__ __forceinline__ void kb_pass_chunk(const BatchArgs& B, PassShared<BLK
   A.s = s;
   A.R = uniform(J.R[k]);
   A.rs_k = (k > 0 && A.R >= 1) ? k : 0;
+  A.t = t;
+  A.since = MASKED ? 0 : since;
   A.step = uniform(J.step);
   const int ne = pass_block<BLK, MASKED>(L, A, c - uniform(J.tchunk0), sh);
   count_evals(uniform(J.evals), ne);
@@ -840,14 +859,15 @@ __device__ __forceinline__ void kb_pass_chunk(const BatchArgs& B, PassShared<BLK
 // keeps the register count, and so the occupancy, of the single-clip pass.
 template <int BLK, bool MASKED, bool PERSIST>
 __global__ __launch_bounds__(BLK) void kb_pass(BatchArgs B, int32_t s, int32_t k, int32_t parity,
-                                               int32_t slot) {
+                                               int32_t slot, int32_t t, int32_t since) {
   __shared__ PassShared<BLK> sh;
   const int32_t n = B.counts[0];
   if (PERSIST) {
-    FOR_EACH_CHUNK(B.queue + slot, n, false, c) kb_pass_chunk<BLK, MASKED>(B, sh, c, s, k, parity);
+    FOR_EACH_CHUNK(B.queue + slot, n, false, c)
+        kb_pass_chunk<BLK, MASKED>(B, sh, c, s, k, parity, t, since);
   } else {
     const int32_t c = xcd_block(blockIdx.x, gridDim.x);
-    if (c < n) kb_pass_chunk<BLK, MASKED>(B, sh, c, s, k, parity);
+    if (c < n) kb_pass_chunk<BLK, MASKED>(B, sh, c, s, k, parity, t, since);
   }
 }
 
@@ -1327,30 +1347,32 @@ void launch_batch_s0(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, 
 
 template <bool M, bool P>
 static void batch_pass_shape(hipStream_t st, const BatchArgs& B, int blk, int32_t grid,
-                             int32_t s, int32_t k, int32_t parity, int32_t slot) {
+                             int32_t s, int32_t k, int32_t parity, int32_t slot, int32_t t,
+                             int32_t since) {
   if (blk == 64)
-    kb_pass<64, M, P><<<grid, 64, 0, st>>>(B, s, k, parity, slot);
+    kb_pass<64, M, P><<<grid, 64, 0, st>>>(B, s, k, parity, slot, t, since);
   else if (blk == 128)
-    kb_pass<128, M, P><<<grid, 128, 0, st>>>(B, s, k, parity, slot);
+    kb_pass<128, M, P><<<grid, 128, 0, st>>>(B, s, k, parity, slot, t, since);
   else
-    kb_pass<256, M, P><<<grid, 256, 0, st>>>(B, s, k, parity, slot);
+    kb_pass<256, M, P><<<grid, 256, 0, st>>>(B, s, k, parity, slot, t, since);
 }
 
 template <bool M>
 static void batch_pass(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t s,
-                       int32_t k, int32_t parity, int32_t slot) {
+                       int32_t k, int32_t parity, int32_t slot, int32_t t, int32_t since) {
   if (B.direct)
-    batch_pass_shape<M, false>(st, B, blk, grid, s, k, parity, slot);
+    batch_pass_shape<M, false>(st, B, blk, grid, s, k, parity, slot, t, since);
   else
-    batch_pass_shape<M, true>(st, B, blk, grid, s, k, parity, slot);
+    batch_pass_shape<M, true>(st, B, blk, grid, s, k, parity, slot, t, since);
 }
 
 void launch_batch_pass(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t s,
-                       int32_t k, int32_t parity, int32_t slot, bool masked) {
+                       int32_t k, int32_t parity, int32_t slot, int32_t t, int32_t since,
+                       bool masked) {
   if (masked)
-    batch_pass<true>(st, B, blk, grid, s, k, parity, slot);
+    batch_pass<true>(st, B, blk, grid, s, k, parity, slot, t, since);
   else
-    batch_pass<false>(st, B, blk, grid, s, k, parity, slot);
+    batch_pass<false>(st, B, blk, grid, s, k, parity, slot, t, since);
 }
 
 void launch_batch_copy(hipStream_t st, const BatchArgs& B, int blk, int32_t grid, int32_t slot) {
