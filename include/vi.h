@@ -243,7 +243,7 @@ vi_status vi_reset_counters(vi_ctx* ctx);
  * pair (launches > 1; their average duration is ms / launches). */
 typedef enum {
   VI_K_INIT = 0,   /* search step 0; units = targets */
-  VI_K_PASS = 1,   /* propagation / random-search pass; units = nominal evals */
+  VI_K_PASS = 1,   /* propagation / random-search pass; units = targets x passes */
   VI_K_RECON = 2,  /* reconstruction; units = hole pixels */
   VI_K_OTHER = 3,  /* upsampling, copies; units = voxels */
   VI_K_ONION = 4   /* any launch of the onion-peel initialisation */

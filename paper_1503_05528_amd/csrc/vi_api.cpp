@@ -274,7 +274,7 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
       A.t = ++t;
       A.since = (!excl && c->prm.n_jf > 0 && t > np) ? t - np : 0;
       vi::launch_pass(c->st, d, A);
-      pass_units += (int64_t)nS * ((A.s > 0 ? 6 : 0) + (A.rs_k > 0 ? 1 : 0));
+      pass_units += (int64_t)nS;
       ++n_pass;
       VI_TRY(launched("pass"));
       cur ^= 1;
