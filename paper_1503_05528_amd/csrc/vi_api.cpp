@@ -270,9 +270,9 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
       A.R = R;
       // passes are numbered from 1 within the search; a target may keep its
       // match without evaluating when nothing around it changed since the
-      // previous pass at the same stride (unmasked searches only)
+      // previous pass at the same stride
       A.t = ++t;
-      A.since = (!excl && c->prm.n_jf > 0 && t > np) ? t - np : 0;
+      A.since = (c->prm.n_jf > 0 && t > np) ? t - np : 0;
       vi::launch_pass(c->st, d, A);
       pass_units += (int64_t)nS;
       ++n_pass;
@@ -958,7 +958,7 @@ vi_status batch_enqueue_iteration(vi_batch* b, bool masked = false) {
       ++t;
       vi::launch_batch_pass(b->st, B, b->blk, grid, b->sched.jf_steps[js],
                             js == njf - 1 ? k : 0, parity, slot++, t,
-                            (!masked && t > njf) ? t - njf : 0, masked);
+                            t > njf ? t - njf : 0, masked);
       parity ^= 1;
     }
   if (parity) vi::launch_batch_copy(b->st, B, b->blk, grid, slot++);

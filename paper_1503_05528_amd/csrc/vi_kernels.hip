@@ -345,23 +345,25 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
     int32_t cq[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) cq[j] = A.nin[qi[j]].x;
-    // Within a search the video is fixed, so distances are.  A target whose
-    // match is unchanged since its previous pass at this stride, and whose
-    // six neighbours' matches are unchanged since before that pass, sees
-    // exactly the candidates that lost to its match then: it keeps it.  A
-    // neighbour's entry read while it is being rewritten only holds this
-    // pass (no skip).  Entries outside the target set are never written.
-    bool stable = !MASKED && A.since > 0 && active && L.chg[p] <= A.since;
-    if (!MASKED && A.since > 0) {
-      uint16_t cg[6];
+    uint16_t cg[6];
+    if (A.since > 0) {
 #pragma unroll
       for (int j = 0; j < 6; ++j) cg[j] = L.chg[qi[j]];
-#pragma unroll
-      for (int j = 0; j < 6; ++j) stable = stable && cg[j] < A.since;
     }
     if (MASKED) {
 #pragma unroll
       for (int j = 0; j < 6; ++j) qok[j] = qok[j] && A.smask[qi[j]] != 0;
+    }
+    // Within a search the video is fixed, so distances are.  A target whose
+    // match is unchanged since its previous pass at this stride, and whose
+    // neighbours in the target set are unchanged since before that pass,
+    // sees exactly the candidates that lost to its match then: it keeps it.
+    // A neighbour's mark read while it is being rewritten only holds this
+    // pass (no skip).  Neighbours outside the target set give no candidate.
+    bool stable = A.since > 0 && active && L.chg[p] <= A.since;
+    if (A.since > 0) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) stable = stable && (!qok[j] || cg[j] < A.since);
     }
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
@@ -847,7 +849,7 @@ __device__ __forceinline__ void kb_pass_chunk(const BatchArgs& B, PassShared<BLK
   A.R = uniform(J.R[k]);
   A.rs_k = (k > 0 && A.R >= 1) ? k : 0;
   A.t = t;
-  A.since = MASKED ? 0 : since;
+  A.since = since;
   A.step = uniform(J.step);
   const int ne = pass_block<BLK, MASKED>(L, A, c - uniform(J.tchunk0), sh);
   count_evals(uniform(J.evals), ne);
