@@ -255,7 +255,9 @@ typedef struct {
   float ms;
   int32_t launches; /* launches the record covers */
 } vi_kernel_time;
-vi_status vi_profile(vi_ctx* ctx, int32_t on);
+/* kinds: bit mask of the vi_kernel_kind values timed (1 << kind), 0 = off */
+#define VI_PROFILE_ALL 0x1F
+vi_status vi_profile(vi_ctx* ctx, int32_t kinds);
 /* Copies up to cap records (host) of the launches timed since the last read
  * and clears them; returns the number of records or a negative status.
  * Syncs. */

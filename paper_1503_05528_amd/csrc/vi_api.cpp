@@ -73,7 +73,7 @@ struct vi_ctx {
   // work counters (host side; effective evaluations live in d_cnt[1..3])
   int64_t n_nominal = 0, n_searches = 0, n_em = 0, n_recon = 0;
   // kernel timing with events on the context's stream
-  bool profiling = false;
+  uint32_t prof_mask = 0;  // kernel kinds timed (bit 1 << vi_kernel_kind)
   int32_t kind_override = -1;  // every launch of the onion peel is VI_K_ONION
   struct Rec {
     int32_t kind, level;
@@ -121,9 +121,11 @@ vi_status launched(const char* what) {
   return VI_OK;
 }
 
-// event pair around a launch while profiling; returns the record index or -1
-int prof_begin(vi_ctx* c) {
-  if (!c->profiling) return -1;
+// event pair around a launch of this kind while it is timed; returns the
+// record index or -1
+int prof_begin(vi_ctx* c, int32_t kind) {
+  const int32_t k = c->kind_override >= 0 ? c->kind_override : kind;
+  if (!(c->prof_mask & (1u << k))) return -1;
   const size_t need = 2 * (c->recs.size() + 1);
   while (c->events.size() < need) {
     hipEvent_t e = vi::event_get(c->dev);
@@ -245,7 +247,7 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
   A.evals = ev_init;
   A.nin = d.nnf0;
   A.nout = d.nnf0;
-  int r = prof_begin(c);
+  int r = prof_begin(c, VI_K_INIT);
   vi::launch_s0(c->st, d, A);
   A.evals = ev_pass;
   prof_end(c, r, VI_K_INIT, level, nS);
@@ -253,7 +255,7 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
   int2* buf[2] = {d.nnf0, d.nnf1};
   int cur = 0;
   // the passes run back to back: one event pair covers all of them
-  r = prof_begin(c);
+  r = prof_begin(c, VI_K_PASS);
   int64_t pass_units = 0;
   int32_t n_pass = 0;
   int32_t t = 0;
@@ -285,7 +287,7 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
   else if (r >= 0)
     c->recs.pop_back();
   if (cur == 1) {
-    r = prof_begin(c);
+    r = prof_begin(c, VI_K_OTHER);
     vi::launch_copy_targets(c->st, tlist, nS, d.nnf1, d.nnf0);
     prof_end(c, r, VI_K_OTHER, level, nS);
     VI_TRY(launched("copy"));
@@ -300,7 +302,7 @@ vi_status recon(vi_ctx* c, int32_t level, const int32_t* plist, int32_t nP, cons
   unsigned long long* spread = absdiff ? c->d_cnt : nullptr;
   if (spread) vi::launch_fill_u64(c->st, spread, vi::kCntWords);
   c->n_recon += nP;
-  const int r = prof_begin(c);
+  const int r = prof_begin(c, VI_K_RECON);
   vi::launch_recon(c->st, c->lv[level].d, plist, nP, excl, mode, out_f, spread);
   prof_end(c, r, VI_K_RECON, level, nP);
   if (spread) vi::launch_sum_spread(c->st, spread, 1, absdiff);
@@ -372,7 +374,7 @@ vi_status onion(vi_ctx* c, int32_t* layers_run) {
   } kind_guard{c};
   c->kind_override = VI_K_ONION;
   for (;;) {
-    const int r = prof_begin(c);
+    const int r = prof_begin(c, VI_K_OTHER);
     vi::launch_erode3(c->st, Hp, E, c->o_bd, d.W, d.H, d.T);
     vi::launch_dilate5(c->st, c->o_bd, c->o_S, c->o_t1, c->o_t2, d.W, d.H, d.T, Hp);
     prof_end(c, r, VI_K_OTHER, level, d.V);
@@ -399,7 +401,7 @@ vi_status transition(vi_ctx* c, int32_t level) {
   Level& F = c->lv[level];
   Level& C = c->lv[level + 1];
   if (!C.complete) return fail(VI_E_STATE, "the coarser level has no complete shift map");
-  const int r = prof_begin(c);
+  const int r = prof_begin(c, VI_K_OTHER);
   vi::launch_upsample(c->st, F.d, C.d, F.tlist, F.nS);
   prof_end(c, r, VI_K_OTHER, level, F.nS);
   VI_TRY(launched("upsample"));
@@ -715,7 +717,7 @@ vi_status vi_reset_counters(vi_ctx* c) {
 
 vi_status vi_profile(vi_ctx* c, int32_t on) {
   if (!c) return fail(VI_E_INVAL, "null context");
-  c->profiling = on != 0;
+  c->prof_mask = (uint32_t)on;
   return VI_OK;
 }
 

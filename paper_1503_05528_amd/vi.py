@@ -307,8 +307,16 @@ class Clip:
     def reset_counters(self):
         _check("vi_reset_counters", lib().vi_reset_counters(self.h))
 
-    def profile(self, on: bool = True):
-        _check("vi_profile", lib().vi_profile(self.h, 1 if on else 0))
+    def profile(self, on: bool = True, kinds=None):
+        """Times launches with events: all kinds, or those named in kinds
+        (e.g. ("pass",)); on=False stops."""
+        mask = 0
+        if on:
+            names = kinds if kinds is not None else KERNEL_KINDS.values()
+            for k, name in KERNEL_KINDS.items():
+                if name in names:
+                    mask |= 1 << k
+        _check("vi_profile", lib().vi_profile(self.h, mask))
 
     def profile_read(self, cap: int = 1 << 16):
         buf = (KernelTime * cap)()
