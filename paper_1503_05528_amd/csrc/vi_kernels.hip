@@ -644,14 +644,25 @@ __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __
       const int src_k = a0 ? 0 : 1;
       const int32_t dr = __shfl(src_k == 0 ? dist[0] : dist[1], src_lane);
       const int32_t nr = __shfl(src_k == 0 ? nv[0] : nv[1], src_lane);
+      // with one voxel count for all, delta_q / (2 sigma^2) = dist_q / (2 dist_r):
+      // one reciprocal per pixel instead of a division per contributor
+      const double inv2dr = uni && dr > 0 ? 1.0 / (2.0 * (double)dr) : 0.0;
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         if (!valid[k]) continue;
         if (dr > 0) {
-          const double num = (double)((int64_t)dist[k] * (int64_t)nr);
-          const double den = (double)(2 * (int64_t)dr * (int64_t)nv[k]);
-          const float tq = (float)(num / den);
-          s[k] = expf(-tq);
+          float tq;
+          if (uni) {
+            tq = (float)((double)dist[k] * inv2dr);
+          } else {
+            const double num = (double)((int64_t)dist[k] * (int64_t)nr);
+            const double den = (double)(2 * (int64_t)dr * (int64_t)nv[k]);
+            tq = (float)(num / den);
+          }
+          // hardware exponential: the ceil(3m/4) contributors at or below the
+          // percentile weigh at least e^-1/2, so underflow of the others is
+          // immaterial
+          s[k] = __expf(-tq);
         } else {
           s[k] = dist[k] == 0 ? 1.f : 0.f;
         }
@@ -693,9 +704,12 @@ __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __
         for (int c = 0; c < 6; ++c) acc[c] += __shfl_xor(acc[c], off);
       }
       uint32_t q8[5];
+      // the weighted mean multiplies by one reciprocal; the plain mean (exact
+      // parity) divides
+      const float inv = 1.f / acc[5];
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
-        const float o = acc[c] / acc[5];
+        const float o = MODE == 0 ? acc[c] * inv : acc[c] / acc[5];
         const int qi = (int)floorf(o + 0.5f);
         q8[c] = (uint32_t)(qi > 255 ? 255 : qi);
         if (lane == 0 && out_f) out_f[5 * (size_t)w + c] = o / 255.f;
