@@ -107,7 +107,7 @@ def lib():
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libvi.so not found at {LIB_PATH}: build it with "
-                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+                               "`python paper_1503_05528_amd/build.py`")
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)
