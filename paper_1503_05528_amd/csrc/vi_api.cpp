@@ -46,6 +46,11 @@ struct Level {
   int32_t* hlist = nullptr;
   int32_t* tlist = nullptr;
   bool complete = false;
+  // the last reconstruction of the level was a full unmasked one of mode
+  // recon_last (weighted or mean), and since then only searches (which keep
+  // the reconstruction marks) changed the state: the next one may skip
+  bool recon_ok = false;
+  int32_t recon_last = -1;
 };
 
 }  // namespace
@@ -295,16 +300,29 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
   return VI_OK;
 }
 
+// the next reconstruction epoch of a level (marks are 16-bit, 0 = never)
+void next_epoch(Level& lv) {
+  lv.d.repoch = lv.d.repoch >= 0xFFFF ? 1 : lv.d.repoch + 1;
+}
+
 // absdiff (optional, one word of device memory) receives the pixels' |change|
-// sum, gathered in the spread counter d_cnt[0]
+// sum, gathered in the spread counter d_cnt[0].  A full unmasked weighted or
+// plain reconstruction without float output may keep the pixels whose
+// contributors did not change since the previous one of the same mode.
 vi_status recon(vi_ctx* c, int32_t level, const int32_t* plist, int32_t nP, const uint8_t* excl,
                 int mode, float* out_f, unsigned long long* absdiff) {
+  Level& lv = c->lv[level];
+  const bool full = !excl && plist == lv.hlist && nP == lv.nH && mode != VI_RECON_BEST;
+  const bool skip = full && !out_f && lv.recon_ok && lv.recon_last == mode;
   unsigned long long* spread = absdiff ? c->d_cnt : nullptr;
   if (spread) vi::launch_fill_u64(c->st, spread, vi::kCntWords);
   c->n_recon += nP;
   const int r = prof_begin(c, VI_K_RECON);
-  vi::launch_recon(c->st, c->lv[level].d, plist, nP, excl, mode, out_f, spread);
+  vi::launch_recon(c->st, lv.d, plist, nP, excl, mode, out_f, spread, skip);
   prof_end(c, r, VI_K_RECON, level, nP);
+  next_epoch(lv);
+  lv.recon_ok = full;
+  lv.recon_last = mode;
   if (spread) vi::launch_sum_spread(c->st, spread, 1, absdiff);
   return launched("recon");
 }
@@ -342,6 +360,7 @@ vi_status inpaint_level(vi_ctx* c, int32_t level, int32_t* iters) {
 
 // scratch of the onion peel, empty shift maps, H' = the coarsest hole
 vi_status onion_prepare(vi_ctx* c) {
+  c->lv[c->L - 1].recon_ok = false;  // the shift maps are emptied below
   const vi::DevLevel& d = c->lv[c->L - 1].d;
   const size_t V = (size_t)d.V;
   if (!c->o_Hp) {
@@ -406,6 +425,7 @@ vi_status transition(vi_ctx* c, int32_t level) {
   prof_end(c, r, VI_K_OTHER, level, F.nS);
   VI_TRY(launched("upsample"));
   F.complete = true;
+  F.recon_ok = false;  // the upsampling sets no reconstruction marks
   return recon(c, level, F.hlist, F.nH, nullptr, c->prm.recon_mode, nullptr, nullptr);
 }
 
@@ -444,8 +464,8 @@ size_t vi_footprint_bytes(const vi_params* prm, int32_t W, int32_t H, int32_t T,
   const int64_t V0 = (int64_t)W * H * T;
   for (int l = 0; l < prm->levels; ++l) {
     const int64_t V = w * h * T;
-    // vox 8, hole/dsrc/htil 3, nnf 16, nvox 1, change marks 2, source list 4
-    total += (size_t)V * 34;
+    // vox 8, hole/dsrc/htil 3, nnf 16, nvox 1, change marks 4, source list 4
+    total += (size_t)V * 36;
     // target and hole lists: the dilated hole is at most 125x the hole
     const double fr = hole_fraction * 125.0 < 1.0 ? hole_fraction * 125.0 : 1.0;
     total += (size_t)((double)V * (fr + hole_fraction) * 4.0) + 4096;
@@ -501,10 +521,12 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
         (st = dalloc(c, &d.dsrc, V)) || (st = dalloc(c, &d.htil, V)) ||
         (st = dalloc(c, &d.nnf0, V)) ||
         (st = dalloc(c, &d.nnf1, V)) || (st = dalloc(c, &d.nvox, V)) ||
-        (st = dalloc(c, &d.chg, V)))
+        (st = dalloc(c, &d.chg, V)) || (st = dalloc(c, &d.rmark, V)))
       return bail(st);
-    if (hipMemsetAsync(d.chg, 0, sizeof(uint16_t) * (size_t)V, c->st) != hipSuccess)
+    if (hipMemsetAsync(d.chg, 0, sizeof(uint16_t) * (size_t)V, c->st) != hipSuccess ||
+        hipMemsetAsync(d.rmark, 0, sizeof(uint16_t) * (size_t)V, c->st) != hipSuccess)
       return bail(fail(VI_E_HIP, "clearing the change marks failed"));
+    d.repoch = 1;
     w = (w + 1) / 2;
     h = (h + 1) / 2;
   }
@@ -673,6 +695,7 @@ vi_status vi_get_state(const vi_ctx* c, int32_t level, uint8_t* rgbt, int32_t* c
 vi_status vi_set_state(vi_ctx* c, int32_t level, const uint8_t* rgbt, const int32_t* cand,
                        const int32_t* dist, const uint8_t* nvox) {
   VI_TRY(level_ok(c, level));
+  c->lv[level].recon_ok = false;
   vi::launch_fill_u64(c->st, c->d_u64 + 1, 2);
   vi::launch_set_state(c->st, c->lv[level].d, rgbt, cand, dist, nvox, c->d_u64 + 1);
   VI_TRY(launched("set_state"));
@@ -907,6 +930,7 @@ vi::JobDesc job_for(vi_batch* b, vi_ctx* c, int32_t level, size_t slot, bool scr
   J.nS = lv.nS;
   J.nH = lv.nH;
   J.recon_mode = c->prm.recon_mode;
+  J.recon_skip = lv.recon_ok && lv.recon_last == c->prm.recon_mode ? 1 : 0;
   J.step = (uint64_t)c->em_k;
   J.absdiff = b->d_abs_spread + slot * (size_t)vi::kCntWords;
   J.evals = scratch_evals ? b->d_scratch : c->d_cnt + vi::kCntWords;
@@ -1022,6 +1046,7 @@ vi_status batch_onion(vi_batch* b, std::vector<vi_ctx*> active) {
       J.smask = c->o_S;
       J.excl = Hp[i];
       J.step = (uint64_t(1) << 32) + (uint64_t)layer;
+      J.recon_skip = 0;
       J.evals = c->d_cnt + 3 * (size_t)vi::kCntWords;
       J.evals_init = c->d_cnt + 3 * (size_t)vi::kCntWords;
       c->n_nominal += per_target_evals(c->prm, r_max(c->lv[level].d)) * (int64_t)J.nS;
@@ -1035,6 +1060,11 @@ vi_status batch_onion(vi_batch* b, std::vector<vi_ctx*> active) {
     if (!b->h_jobs.empty()) {
       VI_TRY(batch_upload(b, blk));
       VI_TRY(batch_enqueue_iteration(b, true));
+      for (vi_ctx* c : next) {
+        Level& lv = c->lv[c->L - 1];
+        next_epoch(lv);
+        lv.recon_ok = false;
+      }
     }
     active.swap(next);
     Hp.swap(nH);
@@ -1270,7 +1300,10 @@ vi_status vi_batch_step(vi_batch* b, int32_t* n_done) {
     ++b->steps_run;
     for (size_t j = 0; j < nj; ++j) {
       vi_ctx* c = b->job_ctx[j];
-      const Level& lv = c->lv[c->cur_level];
+      Level& lv = c->lv[c->cur_level];
+      next_epoch(lv);  // this step's full reconstruction of the level
+      lv.recon_ok = true;
+      lv.recon_last = c->prm.recon_mode;
       c->n_nominal += per_target_evals(c->prm, r_max(lv.d)) * (int64_t)lv.nS;
       c->n_searches += 1;
       c->n_em += 1;

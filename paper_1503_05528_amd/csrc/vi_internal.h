@@ -14,6 +14,10 @@
 //   nvox   u8 [V]     number of voxels the stored distance compared
 //   chg    u16 [V]    pass of the current search that last changed the match
 //                     (0 after step 0; 0 outside the target set)
+//   rmark  u16 [V]    reconstruction epoch at which the target's (match,
+//                     distance, count) last changed; a reconstruction of
+//                     epoch e may skip a hole pixel whose 125 contributors
+//                     all hold marks other than e
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -54,6 +58,8 @@ struct DevLevel {
   int2* nnf1;
   uint8_t* nvox;
   uint16_t* chg;
+  uint16_t* rmark;
+  int32_t repoch;  // epoch of the next reconstruction of the level (from 1)
   int32_t lambda;
   uint64_t seed;
 };
@@ -85,7 +91,7 @@ struct JobDesc {
   int32_t tchunk0;  // first target chunk of this job in the flat chunk list
   int32_t pchunk0;  // first pixel chunk
   int32_t recon_mode;
-  int32_t pad_;
+  int32_t recon_skip;  // the reconstruction may skip pixels with unchanged contributors
   const uint8_t* smask;  // target-set membership (masked launches: onion layer)
   const uint8_t* excl;   // voxels excluded from comparisons and votes (onion: H')
   uint64_t step;    // EM index at the level (Philox counter word 1)
@@ -141,8 +147,11 @@ void launch_pass(hipStream_t st, DevLevel L, const PassArgs& A);
 void launch_copy_targets(hipStream_t st, const int32_t* tlist, int32_t nS, const int2* src,
                          int2* dst);
 
+// skip: the previous reconstruction of the level was a full unmasked one of
+// the same mode and nothing but searches changed the state since
 void launch_recon(hipStream_t st, DevLevel L, const int32_t* plist, int32_t nP,
-                  const uint8_t* filt_excl, int mode, float* out_f, unsigned long long* absdiff);
+                  const uint8_t* filt_excl, int mode, float* out_f, unsigned long long* absdiff,
+                  bool skip = false);
 void launch_upsample(hipStream_t st, DevLevel F, DevLevel C, const int32_t* ftlist,
                      int32_t nS);
 

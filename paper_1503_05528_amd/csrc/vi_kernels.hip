@@ -223,7 +223,9 @@ __device__ __forceinline__ int s0_target(const DevLevel& L, const PassArgs& A, i
   int32_t px, py, pt;
   unlin(L, p, px, py, pt);
   int2* nnf = const_cast<int2*>(A.nin);
-  int32_t c = nnf[p].x;
+  const int2 old = nnf[p];
+  const uint8_t n_old = L.nvox[p];
+  int32_t c = old.x;
   if (c < 0 || c >= L.V || !L.dsrc[c]) {
     uint64_t w[4];
     philox4x64_10((uint64_t)p, A.step, 0, ((uint64_t)L.level << 8) | 1u, L.seed, 0, w);
@@ -234,6 +236,7 @@ __device__ __forceinline__ int s0_target(const DevLevel& L, const PassArgs& A, i
   nnf[p] = make_int2(c, (int32_t)d);
   L.nvox[p] = (uint8_t)n;
   L.chg[p] = 0;
+  if (c != old.x || (int32_t)d != old.y || (uint8_t)n != n_old) L.rmark[p] = (uint16_t)L.repoch;
   return 1;
 }
 
@@ -451,7 +454,10 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
       ne += nr;
     }
     A.nout[p] = make_int2(best_c, (int32_t)best_d);
-    if (best_c != inc.x) L.chg[p] = (uint16_t)A.t;
+    if (best_c != inc.x) {
+      L.chg[p] = (uint16_t)A.t;
+      L.rmark[p] = (uint16_t)L.repoch;
+    }
   }
   return ne;
 }
@@ -490,7 +496,7 @@ template <int MODE, bool FILT>
 __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __restrict__ plist,
                                             int32_t w, const uint8_t* __restrict__ excl,
                                             float* __restrict__ out_f,
-                                            unsigned long long& my_abs) {
+                                            unsigned long long& my_abs, bool skip) {
   const int lane = threadIdx.x & 63;
   {
     const int32_t p = plist[w];
@@ -516,11 +522,19 @@ __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __
     }
     int2 nn[2];
     uint8_t nb[2];
+    uint16_t rm[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       nn[k] = L.nnf0[qq[k]];
       nb[k] = L.nvox[qq[k]];
+      rm[k] = skip ? L.rmark[qq[k]] : (uint16_t)0;
       if (FILT) valid[k] = valid[k] && !excl[qq[k]];
+    }
+    // the sources never change: with no contributor changed since the
+    // previous reconstruction of the level, the pixel keeps its value
+    if (skip) {
+      const uint16_t e = (uint16_t)L.repoch;
+      if ((__ballot(valid[0] && rm[0] == e) | __ballot(valid[1] && rm[1] == e)) == 0) return;
     }
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -734,11 +748,12 @@ template <int MODE, bool FILT>
 __global__ __launch_bounds__(kBlock) void k_recon(DevLevel L, const int32_t* __restrict__ plist,
                                                   int32_t nP, const uint8_t* __restrict__ excl,
                                                   float* __restrict__ out_f,
-                                                  unsigned long long* __restrict__ absdiff) {
+                                                  unsigned long long* __restrict__ absdiff,
+                                                  int32_t skip) {
   const int32_t nwaves = gridDim.x * (kBlock / 64);
   unsigned long long my_abs = 0;
   for (int32_t w = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); w < nP; w += nwaves)
-    recon_pixel<MODE, FILT>(L, plist, w, excl, out_f, my_abs);
+    recon_pixel<MODE, FILT>(L, plist, w, excl, out_f, my_abs, skip != 0);
   if (absdiff) add_spread(absdiff, (threadIdx.x & 63) == 0 ? my_abs : 0ull);
 }
 
@@ -911,12 +926,13 @@ __global__ __launch_bounds__(kBlock) void kb_recon(BatchArgs B, int32_t slot) {
     const int32_t base = (c - uniform(J.pchunk0)) * kPixChunk;
     const int32_t end = min(uniform(J.nH), base + kPixChunk);
     const int32_t mode = uniform(J.recon_mode);
+    const bool skip = !FILT && uniform(J.recon_skip) != 0;
     unsigned long long my_abs = 0;
     for (int32_t w = base + (int32_t)(threadIdx.x >> 6); w < end; w += kWaves) {
       if (mode == 1)
-        recon_pixel<1, FILT>(L, hlist, w, excl, nullptr, my_abs);
+        recon_pixel<1, FILT>(L, hlist, w, excl, nullptr, my_abs, skip);
       else
-        recon_pixel<0, FILT>(L, hlist, w, excl, nullptr, my_abs);
+        recon_pixel<0, FILT>(L, hlist, w, excl, nullptr, my_abs, skip);
     }
     add_spread(uniform(J.absdiff), (threadIdx.x & 63) == 0 ? my_abs : 0ull);
   }
@@ -1259,26 +1275,29 @@ void launch_copy_targets(hipStream_t st, const int32_t* tlist, int32_t nS, const
 }
 
 void launch_recon(hipStream_t st, DevLevel L, const int32_t* plist, int32_t nP,
-                  const uint8_t* filt_excl, int mode, float* out_f, unsigned long long* absdiff) {
+                  const uint8_t* filt_excl, int mode, float* out_f, unsigned long long* absdiff,
+                  bool skip) {
   if (nP <= 0) return;
   const int wpb = kBlock / 64;
   int64_t blocks = (nP + wpb - 1) / wpb;
   if (blocks > 8192) blocks = 8192;
   const dim3 g((unsigned)blocks);
+  // only unmasked weighted or plain means may keep unchanged pixels
+  const int32_t sk = skip && !filt_excl && mode != 2 ? 1 : 0;
   if (filt_excl) {
     if (mode == 0)
-      k_recon<0, true><<<g, kBlock, 0, st>>>(L, plist, nP, filt_excl, out_f, absdiff);
+      k_recon<0, true><<<g, kBlock, 0, st>>>(L, plist, nP, filt_excl, out_f, absdiff, 0);
     else if (mode == 1)
-      k_recon<1, true><<<g, kBlock, 0, st>>>(L, plist, nP, filt_excl, out_f, absdiff);
+      k_recon<1, true><<<g, kBlock, 0, st>>>(L, plist, nP, filt_excl, out_f, absdiff, 0);
     else
-      k_recon<2, true><<<g, kBlock, 0, st>>>(L, plist, nP, filt_excl, out_f, absdiff);
+      k_recon<2, true><<<g, kBlock, 0, st>>>(L, plist, nP, filt_excl, out_f, absdiff, 0);
   } else {
     if (mode == 0)
-      k_recon<0, false><<<g, kBlock, 0, st>>>(L, plist, nP, nullptr, out_f, absdiff);
+      k_recon<0, false><<<g, kBlock, 0, st>>>(L, plist, nP, nullptr, out_f, absdiff, sk);
     else if (mode == 1)
-      k_recon<1, false><<<g, kBlock, 0, st>>>(L, plist, nP, nullptr, out_f, absdiff);
+      k_recon<1, false><<<g, kBlock, 0, st>>>(L, plist, nP, nullptr, out_f, absdiff, sk);
     else
-      k_recon<2, false><<<g, kBlock, 0, st>>>(L, plist, nP, nullptr, out_f, absdiff);
+      k_recon<2, false><<<g, kBlock, 0, st>>>(L, plist, nP, nullptr, out_f, absdiff, 0);
   }
 }
 
