@@ -300,9 +300,9 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
   return VI_OK;
 }
 
-// the next reconstruction epoch of a level (marks are 16-bit, 0 = never)
+// the next reconstruction epoch of a level (marks are 8-bit, 0 = never)
 void next_epoch(Level& lv) {
-  lv.d.repoch = lv.d.repoch >= 0xFFFF ? 1 : lv.d.repoch + 1;
+  lv.d.repoch = lv.d.repoch >= 0xFF ? 1 : lv.d.repoch + 1;
 }
 
 // absdiff (optional, one word of device memory) receives the pixels' |change|
@@ -464,8 +464,8 @@ size_t vi_footprint_bytes(const vi_params* prm, int32_t W, int32_t H, int32_t T,
   const int64_t V0 = (int64_t)W * H * T;
   for (int l = 0; l < prm->levels; ++l) {
     const int64_t V = w * h * T;
-    // vox 8, hole/dsrc/htil 3, nnf 16, nvox 1, change marks 4, source list 4
-    total += (size_t)V * 36;
+    // vox 8, hole/dsrc/htil 3, nnf 16, nvox 1, change marks 3, source list 4
+    total += (size_t)V * 35;
     // target and hole lists: the dilated hole is at most 125x the hole
     const double fr = hole_fraction * 125.0 < 1.0 ? hole_fraction * 125.0 : 1.0;
     total += (size_t)((double)V * (fr + hole_fraction) * 4.0) + 4096;
@@ -521,11 +521,13 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
         (st = dalloc(c, &d.dsrc, V)) || (st = dalloc(c, &d.htil, V)) ||
         (st = dalloc(c, &d.nnf0, V)) ||
         (st = dalloc(c, &d.nnf1, V)) || (st = dalloc(c, &d.nvox, V)) ||
-        (st = dalloc(c, &d.chg, V)) || (st = dalloc(c, &d.rmark, V)))
+        (st = dalloc(c, &d.chg, V)) || (st = dalloc(c, &d.rmark, V + 2 * vi::kMarkPad)))
       return bail(st);
     if (hipMemsetAsync(d.chg, 0, sizeof(uint16_t) * (size_t)V, c->st) != hipSuccess ||
-        hipMemsetAsync(d.rmark, 0, sizeof(uint16_t) * (size_t)V, c->st) != hipSuccess)
+        hipMemsetAsync(d.rmark, 0, V + 2 * vi::kMarkPad, c->st) !=
+            hipSuccess)
       return bail(fail(VI_E_HIP, "clearing the change marks failed"));
+    d.rmark += vi::kMarkPad;  // the block is released through the context's list
     d.repoch = 1;
     w = (w + 1) / 2;
     h = (h + 1) / 2;

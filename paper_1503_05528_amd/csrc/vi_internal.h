@@ -14,10 +14,13 @@
 //   nvox   u8 [V]     number of voxels the stored distance compared
 //   chg    u16 [V]    pass of the current search that last changed the match
 //                     (0 after step 0; 0 outside the target set)
-//   rmark  u16 [V]    reconstruction epoch at which the target's (match,
+//   rmark  u8 [V]     reconstruction epoch at which the target's (match,
 //                     distance, count) last changed; a reconstruction of
 //                     epoch e may skip a hole pixel whose 125 contributors
-//                     all hold marks other than e
+//                     all hold marks other than e (16 zero entries of padding
+//                     on both sides, for the 8-byte row loads); epochs run
+//                     1..255 and wrap, so an old mark can only cause a
+//                     recomputation
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -58,7 +61,7 @@ struct DevLevel {
   int2* nnf1;
   uint8_t* nvox;
   uint16_t* chg;
-  uint16_t* rmark;
+  uint8_t* rmark;
   int32_t repoch;  // epoch of the next reconstruction of the level (from 1)
   int32_t lambda;
   uint64_t seed;
@@ -102,6 +105,7 @@ struct JobDesc {
 };
 
 constexpr int kPixChunk = 64;  // hole pixels per chunk of a batched reconstruction
+constexpr size_t kMarkPad = 16;  // zero entries before and after the marks of a level
 
 constexpr int kQueueSlots = 1024;  // chunk counters, one per launch of a batched iteration
 

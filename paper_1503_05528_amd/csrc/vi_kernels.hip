@@ -236,7 +236,7 @@ __device__ __forceinline__ int s0_target(const DevLevel& L, const PassArgs& A, i
   nnf[p] = make_int2(c, (int32_t)d);
   L.nvox[p] = (uint8_t)n;
   L.chg[p] = 0;
-  if (c != old.x || (int32_t)d != old.y || (uint8_t)n != n_old) L.rmark[p] = (uint16_t)L.repoch;
+  if (c != old.x || (int32_t)d != old.y || (uint8_t)n != n_old) L.rmark[p] = (uint8_t)L.repoch;
   return 1;
 }
 
@@ -325,14 +325,17 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
   s_t[tid] = pt;
   __syncthreads();
   int ne = 0;
+  bool stable = false;
+  uint16_t cp = 0;
   if (A.s > 0) {
     const int32_t s = A.s;
     int32_t c[6];
     bool v[6];
     int32_t qi[6];
     bool qok[6];
-    // every load of the gather is unconditional (clamped to p), so the six
-    // neighbour entries, then the six source flags, are fetched together
+    // the gathers are unconditional (clamped to p), so the six neighbours'
+    // marks, then their entries, then the six source flags, are fetched
+    // together
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       const int axis = j >> 1;
@@ -345,11 +348,9 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
       qok[j] = active && inc.y != 0 && qc >= 0 && qc < dim;
       qi[j] = qok[j] ? p + sgn * s * stride : p;
     }
-    int32_t cq[6];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) cq[j] = A.nin[qi[j]].x;
     uint16_t cg[6];
     if (A.since > 0) {
+      cp = active ? L.chg[p] : (uint16_t)0;
 #pragma unroll
       for (int j = 0; j < 6; ++j) cg[j] = L.chg[qi[j]];
     }
@@ -363,10 +364,22 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
     // sees exactly the candidates that lost to its match then: it keeps it.
     // A neighbour's mark read while it is being rewritten only holds this
     // pass (no skip).  Neighbours outside the target set give no candidate.
-    bool stable = A.since > 0 && active && L.chg[p] <= A.since;
+    stable = A.since > 0 && active && cp <= A.since;
     if (A.since > 0) {
 #pragma unroll
       for (int j = 0; j < 6; ++j) stable = stable && (!qok[j] || cg[j] < A.since);
+    }
+    // a stable target needs neither its neighbours' matches nor the source
+    // flags of their candidates
+    int32_t cq[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      qok[j] = qok[j] && !stable;
+      cq[j] = -1;
+    }
+    if (!stable) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) cq[j] = A.nin[qi[j]].x;
     }
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
@@ -381,10 +394,14 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
     }
     uint8_t ds[6];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) ds[j] = L.dsrc[qok[j] ? c[j] : 0];
+    for (int j = 0; j < 6; ++j) ds[j] = 0;
+    if (!stable) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) ds[j] = L.dsrc[qok[j] ? c[j] : 0];
+    }
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      bool ok = !stable && qok[j] && ds[j] && c[j] != inc.x;
+      bool ok = qok[j] && ds[j] && c[j] != inc.x;
 #pragma unroll
       for (int k = 0; k < 6; ++k)
         if (k < j) ok = ok && !(v[k] && c[k] == c[j]);
@@ -453,10 +470,13 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
       }
       ne += nr;
     }
-    A.nout[p] = make_int2(best_c, (int32_t)best_d);
+    // A stable target unchanged for two passes already holds this entry in
+    // both buffers: the write is skipped.
+    if (!(stable && (int32_t)cp + 2 <= A.t && best_c == inc.x))
+      A.nout[p] = make_int2(best_c, (int32_t)best_d);
     if (best_c != inc.x) {
       L.chg[p] = (uint16_t)A.t;
-      L.rmark[p] = (uint16_t)L.repoch;
+      L.rmark[p] = (uint8_t)L.repoch;
     }
   }
   return ne;
@@ -496,7 +516,7 @@ template <int MODE, bool FILT>
 __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __restrict__ plist,
                                             int32_t w, const uint8_t* __restrict__ excl,
                                             float* __restrict__ out_f,
-                                            unsigned long long& my_abs, bool skip) {
+                                            unsigned long long& my_abs) {
   const int lane = threadIdx.x & 63;
   {
     const int32_t p = plist[w];
@@ -522,19 +542,11 @@ __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __
     }
     int2 nn[2];
     uint8_t nb[2];
-    uint16_t rm[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       nn[k] = L.nnf0[qq[k]];
       nb[k] = L.nvox[qq[k]];
-      rm[k] = skip ? L.rmark[qq[k]] : (uint16_t)0;
       if (FILT) valid[k] = valid[k] && !excl[qq[k]];
-    }
-    // the sources never change: with no contributor changed since the
-    // previous reconstruction of the level, the pixel keeps its value
-    if (skip) {
-      const uint16_t e = (uint16_t)L.repoch;
-      if ((__ballot(valid[0] && rm[0] == e) | __ballot(valid[1] && rm[1] == e)) == 0) return;
     }
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -744,6 +756,60 @@ __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __
   }
 }
 
+typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+
+// The hole pixels w0 + i*stride (i < 64, below end) that a reconstruction of
+// epoch L.repoch has to recompute, as a wave mask (bit i): those with a
+// contributor (a target of the 5x5x5 box around the pixel) whose mark is the
+// epoch.  Lane i checks pixel i: the five marks of each of the 25 rows come
+// with one 8-byte load from the multiple of 4 at or below the row's first
+// entry (the mark array holds 16 entries of padding on both sides); a byte
+// equal to the epoch sets the top bit of its flag byte (exact, no carry
+// crosses bytes), and entries outside the volume are masked.  With skip
+// false every pixel below end is returned.
+__device__ __forceinline__ uint64_t recon_todo(const DevLevel& L,
+                                               const int32_t* __restrict__ plist, int32_t w0,
+                                               int32_t stride, int32_t end, bool skip) {
+  const int lane = threadIdx.x & 63;
+  const int32_t w = w0 + lane * stride;
+  bool todo = w < end;
+  if (skip && todo) {
+    const int32_t p = plist[w];
+    int32_t px, py, pt;
+    unlin(L, p, px, py, pt);
+    const uint32_t ee = (uint32_t)L.repoch * 0x01010101u;
+    // flag bytes k = 0..4 (x offsets -2..2) inside the volume
+    const int klo = px < 2 ? 2 - px : 0;
+    const int khi = px + 2 >= L.W ? L.W + 1 - px : 4;
+    uint64_t km = 0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+      if (k >= klo && k <= khi) km |= 0x80ull << (8 * k);
+    uint64_t acc = 0;
+#pragma unroll
+    for (int dt = -2; dt <= 2; ++dt) {
+      const int32_t qt = pt + dt;
+#pragma unroll
+      for (int dy = -2; dy <= 2; ++dy) {
+        const int32_t qy = py + dy;
+        if (qt < 0 || qt >= L.T || qy < 0 || qy >= L.H) continue;
+        const int32_t qb = (qt * L.H + qy) * L.W + px - 2;  // >= -2
+        const int32_t a = qb & ~3;
+        const u32x2_a4 m = *reinterpret_cast<const u32x2_a4*>(L.rmark + a);
+        uint32_t z[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const uint32_t x = m[j] ^ ee;
+          z[j] = ~(((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x | 0x7f7f7f7fu);
+        }
+        acc |= ((uint64_t)z[1] << 32 | z[0]) >> (8 * (qb - a));
+      }
+    }
+    todo = (acc & km) != 0;
+  }
+  return __ballot(todo);
+}
+
 template <int MODE, bool FILT>
 __global__ __launch_bounds__(kBlock) void k_recon(DevLevel L, const int32_t* __restrict__ plist,
                                                   int32_t nP, const uint8_t* __restrict__ excl,
@@ -752,8 +818,16 @@ __global__ __launch_bounds__(kBlock) void k_recon(DevLevel L, const int32_t* __r
                                                   int32_t skip) {
   const int32_t nwaves = gridDim.x * (kBlock / 64);
   unsigned long long my_abs = 0;
-  for (int32_t w = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); w < nP; w += nwaves)
-    recon_pixel<MODE, FILT>(L, plist, w, excl, out_f, my_abs, skip != 0);
+  // the wave's pixels w, w + nwaves, ... in groups of 64
+  for (int32_t w0 = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); w0 < nP;
+       w0 += 64 * nwaves) {
+    uint64_t todo = recon_todo(L, plist, w0, nwaves, nP, skip != 0);
+    while (todo) {
+      const int i = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      recon_pixel<MODE, FILT>(L, plist, w0 + i * nwaves, excl, out_f, my_abs);
+    }
+  }
   if (absdiff) add_spread(absdiff, (threadIdx.x & 63) == 0 ? my_abs : 0ull);
 }
 
@@ -928,11 +1002,16 @@ __global__ __launch_bounds__(kBlock) void kb_recon(BatchArgs B, int32_t slot) {
     const int32_t mode = uniform(J.recon_mode);
     const bool skip = !FILT && uniform(J.recon_skip) != 0;
     unsigned long long my_abs = 0;
-    for (int32_t w = base + (int32_t)(threadIdx.x >> 6); w < end; w += kWaves) {
+    // kPixChunk / kWaves (<= 64) pixels per wave
+    const int32_t w0 = base + (int32_t)(threadIdx.x >> 6);
+    uint64_t todo = recon_todo(L, hlist, w0, kWaves, end, skip);
+    while (todo) {
+      const int i = __builtin_ctzll(todo);
+      todo &= todo - 1;
       if (mode == 1)
-        recon_pixel<1, FILT>(L, hlist, w, excl, nullptr, my_abs, skip);
+        recon_pixel<1, FILT>(L, hlist, w0 + i * kWaves, excl, nullptr, my_abs);
       else
-        recon_pixel<0, FILT>(L, hlist, w, excl, nullptr, my_abs, skip);
+        recon_pixel<0, FILT>(L, hlist, w0 + i * kWaves, excl, nullptr, my_abs);
     }
     add_spread(uniform(J.absdiff), (threadIdx.x & 63) == 0 ? my_abs : 0ull);
   }
