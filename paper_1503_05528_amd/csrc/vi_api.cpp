@@ -364,8 +364,11 @@ vi_status onion_prepare(vi_ctx* c) {
   const vi::DevLevel& d = c->lv[c->L - 1].d;
   const size_t V = (size_t)d.V;
   if (!c->o_Hp) {
-    VI_TRY(dalloc(c, &c->o_Hp, V));
-    VI_TRY(dalloc(c, &c->o_E, V));
+    // exclusion masks: padded for the 8-byte row loads of the distance
+    VI_TRY(dalloc(c, &c->o_Hp, V + 2 * vi::kMarkPad));
+    VI_TRY(dalloc(c, &c->o_E, V + 2 * vi::kMarkPad));
+    c->o_Hp += vi::kMarkPad;
+    c->o_E += vi::kMarkPad;
     VI_TRY(dalloc(c, &c->o_bd, V));
     VI_TRY(dalloc(c, &c->o_S, V));
     VI_TRY(dalloc(c, &c->o_t1, V));
@@ -517,7 +520,7 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
     d.lambda = prm->lambda;
     d.seed = prm->seed;
     const size_t V = (size_t)d.V;
-    if ((st = dalloc(c, &d.vox, V)) || (st = dalloc(c, &d.hole, V)) ||
+    if ((st = dalloc(c, &d.vox, V + 2 * vi::kVoxPad)) || (st = dalloc(c, &d.hole, V)) ||
         (st = dalloc(c, &d.dsrc, V)) || (st = dalloc(c, &d.htil, V)) ||
         (st = dalloc(c, &d.nnf0, V)) ||
         (st = dalloc(c, &d.nnf1, V)) || (st = dalloc(c, &d.nvox, V)) ||
@@ -527,7 +530,9 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
         hipMemsetAsync(d.rmark, 0, V + 2 * vi::kMarkPad, c->st) !=
             hipSuccess)
       return bail(fail(VI_E_HIP, "clearing the change marks failed"));
-    d.rmark += vi::kMarkPad;  // the block is released through the context's list
+    // the blocks are released through the context's list
+    d.rmark += vi::kMarkPad;
+    d.vox += vi::kVoxPad;
     d.repoch = 1;
     w = (w + 1) / 2;
     h = (h + 1) / 2;

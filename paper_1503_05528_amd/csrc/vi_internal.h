@@ -2,7 +2,9 @@
 //
 // Per pyramid level the context keeps, in HBM:
 //   vox    uint2 [V]  .x = R | G<<8 | B<<16, .y = Tx | Ty<<8 (one 8-byte load
-//                     per voxel feeds two v_dot4_u32_u8 operations)
+//                     per voxel feeds two v_dot4_u32_u8 operations); two
+//                     entries of padding on both sides (row loads of patches
+//                     that cross the volume's first or last row)
 //   hole   u8 [V]     H^l
 //   dsrc   u8 [V]     D~^l (centres of hole-free, in-volume patches)
 //   htil   u8 [V]     H~^l (targets of the shift map)
@@ -106,6 +108,8 @@ struct JobDesc {
 
 constexpr int kPixChunk = 64;  // hole pixels per chunk of a batched reconstruction
 constexpr size_t kMarkPad = 16;  // zero entries before and after the marks of a level
+// (and the onion's exclusion masks)
+constexpr size_t kVoxPad = 2;    // voxel entries before and after a level's video
 
 constexpr int kQueueSlots = 1024;  // chunk counters, one per launch of a batched iteration
 

@@ -107,6 +107,7 @@ __device__ __forceinline__ void acc_voxel(SsdAcc& q, uint2 a, uint2 b) {
 // and one 8-byte load.  The pointer is only 8-byte aligned and the type says
 // so: the compiler picks the widest loads that alignment allows.
 typedef uint32_t u32x4_a8 __attribute__((ext_vector_type(4), aligned(8)));
+typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
 
 struct Row5 {
   uint2 v[5];
@@ -138,15 +139,40 @@ __device__ __forceinline__ void ssd_row(const DevLevel& L, const uint8_t* __rest
     const Row5 a = load_row5(vox + (p + row - 2));
 #pragma unroll
     for (int k = 0; k < 5; ++k) acc_voxel(q, a.v[k], b.v[k]);
+  } else if (MASKED) {
+    // the target row with one row load as well (the voxel array holds two
+    // entries of padding on both sides) and its five exclusion bytes with
+    // one 8-byte load (the mask holds 16 bytes of padding on both sides);
+    // entries outside the volume or excluded are masked
+    const int32_t tt = pt + dt, yy = py + dy;
+    const bool rok = tt >= 0 && tt < L.T && yy >= 0 && yy < L.H;
+    const int32_t base = (rok ? p + row : p) - 2;
+    const Row5 a = load_row5(vox + base);
+    const int klo = px < 2 ? 2 - px : 0;
+    const int khi = px + 2 >= L.W ? L.W + 1 - px : 4;
+    uint32_t okm = rok ? ((0x1fu << klo) & (0x1fu >> (4 - khi))) : 0u;
+    const int32_t al = base & ~3;
+    const u32x2_a4 e = *reinterpret_cast<const u32x2_a4*>(excl + al);
+    const uint64_t e64 = ((uint64_t)e[1] << 32 | e[0]) >> (8 * (base - al));
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+      if ((e64 >> (8 * k)) & 0xffu) okm &= ~(1u << k);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const bool ok = (okm >> k) & 1u;
+      q.n += ok ? 1 : 0;
+      acc_voxel(q, ok ? a.v[k] : make_uint2(0, 0), ok ? b.v[k] : make_uint2(0, 0));
+    }
   } else {
+    // voxel by voxel: fewer registers than a masked row (the unmasked pass
+    // keeps its occupancy)
     const int32_t tt = pt + dt, yy = py + dy;
     const bool rok = tt >= 0 && tt < L.T && yy >= 0 && yy < L.H;
 #pragma unroll
     for (int dx = -2; dx <= 2; ++dx) {
       const int32_t xx = px + dx;
-      bool ok = rok && xx >= 0 && xx < L.W;
+      const bool ok = rok && xx >= 0 && xx < L.W;
       const int32_t ai = ok ? p + row + dx : p;
-      if (MASKED) ok = ok && !excl[ai];
       uint2 a = vox[ai];
       uint2 bb = b.v[dx + 2];
       if (!ok) {
@@ -755,8 +781,6 @@ __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __
     }
   }
 }
-
-typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
 
 // The hole pixels w0 + i*stride (i < 64, below end) that a reconstruction of
 // epoch L.repoch has to recompute, as a wave mask (bit i): those with a
