@@ -835,11 +835,12 @@ __device__ __forceinline__ uint64_t recon_todo(const DevLevel& L,
 }
 
 template <int MODE, bool FILT>
-__global__ __launch_bounds__(kBlock) void k_recon(DevLevel L, const int32_t* __restrict__ plist,
-                                                  int32_t nP, const uint8_t* __restrict__ excl,
-                                                  float* __restrict__ out_f,
-                                                  unsigned long long* __restrict__ absdiff,
-                                                  int32_t skip) {
+// Eight waves per SIMD: the code fits in 64 VGPRs without spilling vector
+// registers, and a reconstruction is bound by each wave's chain of fetches.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void k_recon(DevLevel L, const int32_t* __restrict__ plist, int32_t nP,
+             const uint8_t* __restrict__ excl, float* __restrict__ out_f,
+             unsigned long long* __restrict__ absdiff, int32_t skip) {
   const int32_t nwaves = gridDim.x * (kBlock / 64);
   unsigned long long my_abs = 0;
   // the wave's pixels w, w + nwaves, ... in groups of 64
@@ -1013,7 +1014,9 @@ __global__ __launch_bounds__(BLK) void kb_copy(BatchArgs B, int32_t slot) {
 }
 
 template <bool FILT>
-__global__ __launch_bounds__(kBlock) void kb_recon(BatchArgs B, int32_t slot) {
+// eight waves per SIMD, as k_recon
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void kb_recon(BatchArgs B, int32_t slot) {
   constexpr int kWaves = kBlock / 64;
   const int32_t n = B.counts[1];
   FOR_EACH_CHUNK(B.queue + slot, n, B.direct, c) {
