@@ -169,7 +169,9 @@ def test_reconstruct_parity(vi, name, mode):
             assert os_ == int(host(gs)[0])
 
 
-@pytest.mark.parametrize("name", ["tiny", "small2", "small3"])
+# "edge": masked distances whose rows start before the first voxel or end
+# after the last one of the volume
+@pytest.mark.parametrize("name", ["tiny", "small2", "small3", "edge"])
 def test_onion_mean_bitexact(vi, name):
     clip, L = CLIPS[name]()
     o, g = make_pair(vi, clip, levels=L, seed=4, recon_mode=1)
