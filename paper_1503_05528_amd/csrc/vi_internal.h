@@ -106,7 +106,7 @@ struct JobDesc {
   int32_t R[kMaxPmIters + 1];  // random-search radius of iteration k
 };
 
-constexpr int kPixChunk = 64;  // hole pixels per chunk of a batched reconstruction
+constexpr int kPixChunk = 256;  // hole pixels per chunk of a batched reconstruction
 constexpr size_t kMarkPad = 16;  // zero entries before and after the marks of a level
 // (and the onion's exclusion masks)
 constexpr size_t kVoxPad = 2;    // voxel entries before and after a level's video
