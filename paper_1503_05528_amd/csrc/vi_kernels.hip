@@ -196,11 +196,21 @@ __device__ __forceinline__ uint32_t ssd_groups(const DevLevel& L, const uint8_t*
   SsdAcc q{0u, 0u, 0};
   const uint32_t lam = (uint32_t)L.lambda;
   ssd_row<FULL, MASKED>(L, excl, p, px, py, pt, c, 0, 0, q);
+  if (ABORT) {
 #pragma unroll 1
-  for (int r = 1; r < 25; r += 2) {
-    if (ABORT && q.sc + lam * q.st > abort_above) break;
-    ssd_row<FULL, MASKED>(L, excl, p, px, py, pt, c, kRowDt[r], kRowDy[r], q);
-    ssd_row<FULL, MASKED>(L, excl, p, px, py, pt, c, kRowDt[r + 1], kRowDy[r + 1], q);
+    for (int r = 1; r < 25; r += 2) {
+      if (q.sc + lam * q.st > abort_above) break;
+      ssd_row<FULL, MASKED>(L, excl, p, px, py, pt, c, kRowDt[r], kRowDy[r], q);
+      ssd_row<FULL, MASKED>(L, excl, p, px, py, pt, c, kRowDt[r + 1], kRowDy[r + 1], q);
+    }
+  } else {
+    // without early exit nothing orders the rows: four in flight at a time
+#pragma unroll 1
+    for (int r = 1; r < 25; r += 4) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        ssd_row<FULL, MASKED>(L, excl, p, px, py, pt, c, kRowDt[r + j], kRowDy[r + j], q);
+    }
   }
   nvox = FULL ? 125 : q.n;
   return q.sc + lam * q.st;
