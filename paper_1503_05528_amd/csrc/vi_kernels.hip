@@ -228,6 +228,35 @@ __device__ __forceinline__ uint32_t patch_ssd(const DevLevel& L, const uint8_t* 
   return ssd_groups<false, MASKED, ABORT>(L, excl, p, px, py, pt, c, abort_above, nvox);
 }
 
+// Wave-wide reductions with DPP row operations instead of LDS permutes:
+// adjacent lanes, quads, half rows and rows of 16 by swizzles within a row,
+// then the four rows through row_bcast:15 (rows 1 and 3) and row_bcast:31
+// (rows 2 and 3), which leaves the total in lane 63; it is read back as a
+// wave-uniform value.  Lanes outside a broadcast's rows receive the neutral
+// element.  Every lane of the wave must be active.
+template <typename Op>
+__device__ __forceinline__ uint32_t dpp_reduce(uint32_t v, Op op) {
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));  // [1,0,3,2]
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));  // [2,3,0,1]
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // half mirror
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // mirror
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));  // bcast 15
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));  // bcast 31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// float sum over the wave (the order of the additions is fixed: sums of
+// integers below 2^24 are exact)
+__device__ __forceinline__ float wave_sum_f32(float x) {
+  return __uint_as_float(dpp_reduce(__float_as_uint(x), [](uint32_t a, uint32_t b) {
+    return __float_as_uint(__uint_as_float(a) + __uint_as_float(b));
+  }));
+}
+
+__device__ __forceinline__ uint32_t wave_or_u32(uint32_t x) {
+  return dpp_reduce(x, [](uint32_t a, uint32_t b) { return a | b; });
+}
+
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
   return v;
@@ -657,8 +686,7 @@ __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __
       // keys are below 2^31 (distances) or non-negative floats; the walk
       // starts at the highest bit any key has set
       uint32_t any = (valid[0] ? uk[0] : 0u) | (valid[1] ? uk[1] : 0u);
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) any |= (uint32_t)__shfl_xor((int)any, o);
+      any = wave_or_u32(any);
       const int top = any ? 31 - __builtin_clz(any) : -1;
       for (int b = top; b >= 0; --b) {
         const uint64_t t0 = __ballot((uk[0] >> b) & 1u), t1 = __ballot((uk[1] >> b) & 1u);
@@ -761,10 +789,7 @@ __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __
         acc[5] += sk;
       }
 #pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) acc[c] += __shfl_xor(acc[c], off);
-      }
+      for (int c = 0; c < 6; ++c) acc[c] = wave_sum_f32(acc[c]);
       uint32_t q8[5];
       // the weighted mean multiplies by one reciprocal; the plain mean (exact
       // parity) divides
