@@ -479,7 +479,7 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
       const int cnt = __popcll(bal);
       int base = 0;
       if ((tid & 63) == 0 && cnt) base = atomicAdd(&s_nq, cnt);
-      base = __shfl(base, 0);
+      base = __builtin_amdgcn_readlane(base, 0);
       if (v[j]) s_q[base + lane_prefix(bal)] = (uint16_t)(tid | (j << 8));
     }
     __syncthreads();
@@ -648,8 +648,10 @@ __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __
           go = oo;
         }
       }
-      best_lane = go & 63;
-      best_k = go >> 6;
+      // every lane holds the minimum: one wave-uniform copy
+      const int32_t gu = __builtin_amdgcn_readfirstlane(go);
+      best_lane = gu & 63;
+      best_k = gu >> 6;
       (void)bkk;
     } else if (MODE == 1) {
       s[0] = valid[0] ? 1.f : 0.f;
@@ -666,7 +668,7 @@ __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __
       // the distances themselves and no tie needs an exact second look.
       const int fs = a0 ? (int)__ffsll((unsigned long long)a0) - 1
                         : (int)__ffsll((unsigned long long)a1) - 1;
-      const int32_t n_first = __shfl(a0 ? nv[0] : nv[1], fs);
+      const int32_t n_first = __builtin_amdgcn_readlane(a0 ? nv[0] : nv[1], fs);
       const bool uni =
           (__ballot(valid[0] && nv[0] != n_first) | __ballot(valid[1] && nv[1] != n_first)) == 0;
       uint32_t uk[2];
@@ -710,7 +712,10 @@ __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __
       if (!uni) {
         const int gl = a0 ? (int)__ffsll((unsigned long long)a0) - 1
                           : (int)__ffsll((unsigned long long)a1) - 1;
-        const uint64_t kf = __shfl(a0 ? key[0] : key[1], gl);
+        const uint64_t kl = a0 ? key[0] : key[1];
+        const uint64_t kf =
+            (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)kl, gl) |
+            (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(kl >> 32), gl) << 32;
         const bool in0 = (a0 >> lane) & 1ull, in1 = (a1 >> lane) & 1ull;
         if ((__ballot(in0 && key[0] != kf) | __ballot(in1 && key[1] != kf)) != 0) {
           for (int b = 63; b >= 0; --b) {
@@ -732,8 +737,8 @@ __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __
       const int src_lane = a0 ? (int)__ffsll((unsigned long long)a0) - 1
                               : (int)__ffsll((unsigned long long)a1) - 1;
       const int src_k = a0 ? 0 : 1;
-      const int32_t dr = __shfl(src_k == 0 ? dist[0] : dist[1], src_lane);
-      const int32_t nr = __shfl(src_k == 0 ? nv[0] : nv[1], src_lane);
+      const int32_t dr = __builtin_amdgcn_readlane(src_k == 0 ? dist[0] : dist[1], src_lane);
+      const int32_t nr = __builtin_amdgcn_readlane(src_k == 0 ? nv[0] : nv[1], src_lane);
       // with one voxel count for all, delta_q / (2 sigma^2) = dist_q / (2 dist_r):
       // one reciprocal per pixel instead of a division per contributor
       const double inv2dr = uni && dr > 0 ? 1.0 / (2.0 * (double)dr) : 0.0;
@@ -762,8 +767,8 @@ __device__ __forceinline__ void recon_pixel(const DevLevel& L, const int32_t* __
     if (lane == 0) oldv = L.vox[p];
     uint32_t nx, ny;
     if (MODE == 2) {
-      const uint32_t vx0 = __shfl(best_k ? v[1].x : v[0].x, best_lane);
-      const uint32_t vy0 = __shfl(best_k ? v[1].y : v[0].y, best_lane);
+      const uint32_t vx0 = (uint32_t)__builtin_amdgcn_readlane((int)(best_k ? v[1].x : v[0].x), best_lane);
+      const uint32_t vy0 = (uint32_t)__builtin_amdgcn_readlane((int)(best_k ? v[1].y : v[0].y), best_lane);
       nx = vx0;
       ny = vy0;
       if (lane == 0 && out_f) {
