@@ -110,6 +110,10 @@ vi_status vi_nnf_search(vi_ctx* ctx, int32_t level, int32_t em_iter);
  *           order, or NULL.
  *   absdiff (dev) one uint64 receiving sum over H^l of |new - old| over the
  *           three colour channels (the stopping test of Alg. 4), or NULL.
+ * Without out_f, a weighted or plain reconstruction that follows one of the
+ * same mode on the level recomputes only the pixels with a contributing
+ * patch whose match, distance or count changed since; the others already
+ * hold the value it would compute.
  * Errors: VI_E_STATE if the level has no complete shift map. */
 vi_status vi_reconstruct(vi_ctx* ctx, int32_t level, int32_t mode, float* out_f,
                          uint64_t* absdiff);
