@@ -225,10 +225,30 @@ def batched_vs_serial(clips, em_iters):
             "batched_evals_per_s": nominal / t_batch}, service
 
 
+def host_service_times(clips, sd_clip, idxs, em_iters):
+    """Serial service time of each clip as a request sees it: input from host
+    memory to the device, context, inpainting, output back to host memory
+    (index -1: the SD clip)."""
+    import torch
+    from paper_1503_05528_amd import vi
+    out = {}
+    for idx in [idxs[0]] + list(idxs):  # the first run also warms up
+        v, m, L = sd_clip if idx < 0 else clips[idx]
+        torch.cuda.synchronize()
+        s = time.perf_counter()
+        g = vi.Clip(torch.from_numpy(v).cuda(), torch.from_numpy(m).cuda(), levels=L,
+                    em_tol=-1.0, em_max_iters=em_iters, seed=1)
+        g.inpaint().cpu()
+        g.close()
+        out[idx] = time.perf_counter() - s
+    return out
+
+
 def served(clips, sd_clip, seconds, rate, em_iters, service_alone):
     """Poisson arrivals served by the continuous-batching server, against
-    serial FIFO execution of the same trace with the measured per-clip
-    service times."""
+    serial FIFO execution of the same trace: with each clip's serial service
+    time through host memory, as the server's requests arrive and leave, and
+    (for reference) with the device-resident service times service_alone."""
     import threading
     import torch
     from paper_1503_05528_amd import synth
@@ -241,6 +261,8 @@ def served(clips, sd_clip, seconds, rate, em_iters, service_alone):
             jobs.append((t, -1))
         else:
             jobs.append((t, int(rng.integers(0, len(clips)))))
+    log("served: serial service times through host memory")
+    host_svc = host_service_times(clips, sd_clip, sorted({i for _, i in jobs}), em_iters)
     free = torch.cuda.mem_get_info()[0]
     # two lanes: clips of up to 20 M voxels, and larger ones, overlap on the GPU
     lanes = [GpuEngine(), GpuEngine()]
@@ -276,14 +298,16 @@ def served(clips, sd_clip, seconds, rate, em_iters, service_alone):
     for e in lanes:
         e.close()
     st = srv.latency_stats()
-    serial = fifo_latencies([t for t, _ in jobs],
-                            [service_alone[idx] for _, idx in jobs])
+    serial = fifo_latencies([t for t, _ in jobs], [host_svc[idx] for _, idx in jobs])
+    serial_dev = fifo_latencies([t for t, _ in jobs], [service_alone[idx] for _, idx in jobs])
     return {"rate_per_s": rate, "duration_s": seconds, "jobs": len(jobs),
             "sd_jobs": sum(1 for _, i in jobs if i < 0),
             "clips_per_s": len(jobs) / (t_end - t0),
             "p50_s": st.get("p50_s"), "p99_s": st.get("p99_s"),
             "serial_fifo_p50_s": percentile(serial, 0.5),
             "serial_fifo_p99_s": percentile(serial, 0.99),
+            "serial_fifo_device_resident_p50_s": percentile(serial_dev, 0.5),
+            "serial_fifo_device_resident_p99_s": percentile(serial_dev, 0.99),
             "max_running": srv.max_running, "steps": srv.steps,
             "max_admitted_gb": srv.max_admitted_bytes / 2 ** 30}
 
