@@ -1273,10 +1273,50 @@ vi_status vi_batch_step(vi_batch* b, int32_t* n_done) {
   std::vector<vi_ctx*> fresh;
   for (vi_ctx* c : b->members)
     if (c->phase == 0) fresh.push_back(c);
-  if (!fresh.empty()) VI_TRY(batch_onion(b, fresh));
+  if (fresh.size() == 1) {
+    // one clip alone runs the single-clip launches: the same per-target
+    // code and random numbers, without job tables
+    vi_ctx* c = fresh[0];
+    VI_TRY(onion(c, nullptr));
+    c->phase = 1;
+    c->cur_level = c->L - 1;
+    c->em_k = 0;
+  } else if (!fresh.empty()) {
+    VI_TRY(batch_onion(b, fresh));
+  }
   for (vi_ctx* c : b->members) VI_TRY(drive_skip_empty(c));
   bool any = false;
-  for (vi_ctx* c : b->members) any = any || c->phase == 1;
+  vi_ctx* lone = nullptr;
+  int32_t n_em = 0;
+  for (vi_ctx* c : b->members)
+    if (c->phase == 1) {
+      any = true;
+      lone = c;
+      ++n_em;
+    }
+  if (n_em == 1) {
+    // one EM iteration of the only clip in its EM phase, as vi_inpaint_level
+    vi_ctx* c = lone;
+    const int32_t level = c->cur_level;
+    Level& lv = c->lv[level];
+    VI_TRY(search(c, level, lv.tlist, lv.nS, lv.d.htil, nullptr, (uint64_t)c->em_k));
+    VI_TRY(recon(c, level, lv.hlist, lv.nH, nullptr, c->prm.recon_mode, nullptr, c->d_u64));
+    ++b->steps_run;
+    c->n_em += 1;
+    c->em_k += 1;
+    double e = INFINITY;
+    if (c->prm.em_tol >= 0) {
+      unsigned long long s = 0;
+      VI_HIP(hipMemcpyAsync(&s, c->d_u64, sizeof(s), hipMemcpyDeviceToHost, b->st));
+      VI_HIP(hipStreamSynchronize(b->st));
+      e = (double)s / (3.0 * (double)lv.nH);
+    }
+    if (!(e > c->prm.em_tol && c->em_k < c->prm.em_max_iters)) {
+      VI_TRY(drive_finish_level(c));
+      VI_TRY(drive_skip_empty(c));
+    }
+    any = false;
+  }
   if (any) {
     if (!b->tuned) VI_TRY(batch_autotune(b));
     VI_TRY(batch_build(b, b->blk, false));
