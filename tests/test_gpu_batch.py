@@ -115,8 +115,26 @@ def test_batch_counters_match_alone(vi):
     b.add(g2)
     b.run()
     a, bb = g1.counters(), g2.counters()
-    for k in ("nominal_evals", "effective_evals", "searches", "em_iters", "recon_pixels"):
+    for k in ("nominal_evals", "searches", "em_iters", "recon_pixels"):
         assert a[k] == bb[k], k
+    # A pass reads its neighbours' change marks while other workgroups may
+    # be rewriting them; such a read can only cancel a skip (the target then
+    # evaluates candidates that lose), so the count of computed distances
+    # may differ slightly from run to run while every result is the same.
+    assert abs(a["effective_evals"] - bb["effective_evals"]) <= 1e-3 * a["effective_evals"]
+
+
+def test_batch_of_one_matches_alone(vi, references):
+    # a single member runs the single-clip launches: onion and EM steps
+    for i in (1, 3):
+        c, kw = clips()[i]
+        b = vi.Batch(tune=(256, 0))
+        g = vi.Clip(dev(c.occluded_input()), dev(c.mask), **kw)
+        b.add(g)
+        assert b.run() > 1
+        assert np.array_equal(g.output().cpu().numpy(), references[i]), i
+        g.close()
+        b.close()
 
 
 def test_batch_errors(vi):
