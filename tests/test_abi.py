@@ -53,6 +53,12 @@ def test_params_default_and_validation_on_host(libvi):
     assert vi.footprint_bytes(bad, 854, 480, 100, 0.05) == 0
     bad = vi.default_params(levels=6)
     assert vi.footprint_bytes(bad, 64, 64, 10, 0.05) == 0  # coarsest level too small
+    # volumes: at least one patch per axis, fewer than 2^31 voxels (32-bit
+    # voxel indices); the largest admissible one is sized without overflow
+    assert vi.footprint_bytes(p, 4, 480, 100, 0.05) == 0
+    assert vi.footprint_bytes(p, 32767, 32767, 5, 0.05) == 0
+    big = vi.footprint_bytes(p, 2048, 1024, 1023, 0.01)
+    assert big > 2048 * 1024 * 1023 * 36
     h = C.c_void_p()
     # null inputs are rejected before any device work
     st = libvi.vi_create(C.byref(h), C.byref(p), 32, 32, 8, None, None, None)
