@@ -253,18 +253,21 @@ class Server:
                 ok = True
             except Exception as e:
                 out, ok = e, False
-            finally:
-                lane.engine.release(h)
-                with self._lock:
-                    del lane.running[h]
-                    self.used -= need
-                    self._lock.notify_all()
+            # the result is in host memory: it is handed over before the
+            # release, which waits for the work the lane's other jobs queued
             t = self.clock()
             self.records.append(Record(req.rid, req.arrival, t_adm, t, ok))
             if ok:
                 fut.set_result(out)
             else:
                 fut.set_exception(out)
+            try:
+                lane.engine.release(h)
+            finally:
+                with self._lock:
+                    del lane.running[h]
+                    self.used -= need
+                    self._lock.notify_all()
 
     def _loop(self, lane: _Lane):
         while True:
