@@ -504,11 +504,17 @@ def main():
     nominal_pass_per_launch = (nominal - pas["targets_per_search"]) / pas["launches"]
     traffic = None
     hbm_gbs = None
+    achievable = None
     if os.path.exists(COUNTERS_JSON):
         cj = json.load(open(COUNTERS_JSON))
         if cj.get("source_sha256") == kernel_source_hash() and cj.get("workload") == a.config:
             traffic = cj["hbm_bytes_per_launch"]
             hbm_gbs = traffic / (cj["mean_launch_us"] * 1e-6) / 1e9
+        # the rate a plain device copy reaches on the box (read + written),
+        # a property of the hardware, not of the kernel
+        cc = cj.get("copy_calibration")
+        if cc and cc.get("mean_us"):
+            achievable = 2.0 * cc["bytes"] / (cc["mean_us"] * 1e-6) / 1e9
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -521,6 +527,8 @@ def main():
         "nominal_gather_gbs": round(BYTES_PER_EVAL * nominal_pass_per_launch
                                     / (avg_ms * 1e-3) / 1e9, 1),
         "measured_hbm_gbs": None if hbm_gbs is None else round(hbm_gbs, 1),
+        "achievable_copy_gbs": None if achievable is None else round(achievable, 1),
+        "frac_of_achievable": None if achievable is None else round(achieved / achievable, 4),
     }
     line = {
         "metric": "NNF patch-distance evals/s (nominal)",
