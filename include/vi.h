@@ -24,7 +24,7 @@
  *     (t*H_l + y)*W_l + x at level l; level 0 is the finest.
  *   - Colour and texture channels are integers 0..255; a voxel carries five
  *     channels R, G, B, Tx, Ty.
- *   - Limits: W < 32768, H < 32768, T < 32768, W*H*T < 2^31, levels <= 12,
+ *   - Limits: W < 32768, H < 32768, T < 32768, W*H*T < 2^31, levels <= 8,
  *     patch = 5x5x5, 1 <= jump-flood step <= 4, lambda <= 130 (keeps the
  *     integer distance below 2^31).
  */
@@ -142,8 +142,11 @@ vi_status vi_inpaint(vi_ctx* ctx, uint8_t* out_rgb);
  *   the match, -1 outside H~ or unset;  dist [..] int32 integer SSD, -1
  *   outside H~;  nvox [..] uint8 number of compared voxels, 0 outside H~.
  * vi_set_state writes only hole voxels of rgbt and only H~ entries of the
- * map; it syncs to validate cand (VI_E_INVAL if some cand is outside
- * [-1, V)).  A map with every H~ entry in D~ counts as complete. */
+ * map.  It syncs to validate cand first: if some cand is outside [-1, V) it
+ * returns VI_E_INVAL and writes nothing, so the level keeps its previous
+ * state.  After a write, the level counts as complete (vi_reconstruct
+ * accepted) only if every H~ entry of cand is in D~ and, when nvox is given,
+ * every H~ entry of nvox is nonzero. */
 vi_status vi_get_state(const vi_ctx* ctx, int32_t level, uint8_t* rgbt, int32_t* cand,
                        int32_t* dist, uint8_t* nvox);
 vi_status vi_set_state(vi_ctx* ctx, int32_t level, const uint8_t* rgbt, const int32_t* cand,
@@ -212,9 +215,14 @@ typedef struct vi_batch vi_batch;
  * hip_stream: stream for all batch work, or NULL for a stream of its own
  * (graph capture cannot use the legacy default stream). */
 vi_status vi_batch_create(vi_batch** out, const vi_tune* tune, void* hip_stream);
-/* Adds a clip that has not finished; its work moves to the batch's stream.
- * VI_E_BUDGET when the batch holds 1024 clips. */
+/* Adds a clip that has not finished; its work moves to the batch's stream
+ * while it is a member (vi_set_stream then returns VI_E_STATE).
+ * VI_E_BUDGET when the batch holds 1024 clips; VI_E_INVAL when the clip is
+ * already in this or another batch. */
 vi_status vi_batch_add(vi_batch* b, vi_ctx* ctx);
+/* Waits for the batch's queued work, removes the clip and gives it back the
+ * stream it had before vi_batch_add.  vi_destroy of a member does the same
+ * before freeing it. */
 vi_status vi_batch_remove(vi_batch* b, vi_ctx* ctx);
 /* One step of every member; n_done (host) receives the number of members
  * whose work has all been enqueued (their results are final once the stream
@@ -223,7 +231,8 @@ vi_status vi_batch_remove(vi_batch* b, vi_ctx* ctx);
 vi_status vi_batch_step(vi_batch* b, int32_t* n_done);
 vi_status vi_batch_get_tune(const vi_batch* b, vi_tune* out);
 int32_t vi_batch_size(const vi_batch* b);
-/* Frees the batch (not its members); NULL-safe. */
+/* Frees the batch (not its members, which get their own streams back and
+ * stay usable); NULL-safe.  Syncs the batch's stream. */
 void vi_batch_destroy(vi_batch* b);
 
 /* Work counters of a context since creation or the last reset (host out).

@@ -93,9 +93,16 @@ struct vi_ctx {
   int32_t phase = 0;
   int32_t cur_level = -1;
   int32_t em_k = 0;
+  // batch membership: the batch the clip belongs to and the clip's own
+  // stream, given back when it leaves the batch
+  vi_batch* batch = nullptr;
+  hipStream_t own_st = nullptr;
 };
 
 namespace {
+
+// removes a clip from its batch (defined with the batches below)
+void batch_detach(vi_batch* b, vi_ctx* c);
 
 template <typename T>
 vi_status dalloc(vi_ctx* c, T** p, size_t n) {
@@ -588,6 +595,7 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
 
 void vi_destroy(vi_ctx* c) {
   if (!c) return;
+  if (c->batch) batch_detach(c->batch, c);
   // nothing queued uses the blocks after this: they may serve any stream
   (void)hipStreamSynchronize(c->st);
   for (const auto& a : c->allocs) vi::pool_free(c->dev, a.first);
@@ -597,6 +605,7 @@ void vi_destroy(vi_ctx* c) {
 
 vi_status vi_set_stream(vi_ctx* c, void* hip_stream) {
   if (!c) return fail(VI_E_INVAL, "null context");
+  if (c->batch) return fail(VI_E_STATE, "the clip is in a batch: its work runs on the batch's stream");
   c->st = static_cast<hipStream_t>(hip_stream);
   return VI_OK;
 }
@@ -702,15 +711,19 @@ vi_status vi_get_state(const vi_ctx* c, int32_t level, uint8_t* rgbt, int32_t* c
 vi_status vi_set_state(vi_ctx* c, int32_t level, const uint8_t* rgbt, const int32_t* cand,
                        const int32_t* dist, const uint8_t* nvox) {
   VI_TRY(level_ok(c, level));
-  c->lv[level].recon_ok = false;
+  // validate first: a rejected call writes nothing, so the level keeps its
+  // previous (consistent) state and completeness
   vi::launch_fill_u64(c->st, c->d_u64 + 1, 2);
-  vi::launch_set_state(c->st, c->lv[level].d, rgbt, cand, dist, nvox, c->d_u64 + 1);
-  VI_TRY(launched("set_state"));
+  vi::launch_set_state(c->st, c->lv[level].d, rgbt, cand, dist, nvox, c->d_u64 + 1, 0);
+  VI_TRY(launched("set_state check"));
   unsigned long long bad[2] = {0, 0};
   VI_HIP(hipMemcpyAsync(bad, c->d_u64 + 1, sizeof(bad), hipMemcpyDeviceToHost, c->st));
   VI_TRY(sync(c));
   if (bad[0]) return fail(VI_E_INVAL, "cand outside [-1, V)");
-  if (cand) c->lv[level].complete = bad[1] == 0;
+  c->lv[level].recon_ok = false;
+  vi::launch_set_state(c->st, c->lv[level].d, rgbt, cand, dist, nvox, c->d_u64 + 1, 1);
+  VI_TRY(launched("set_state"));
+  if (cand || nvox) c->lv[level].complete = cand ? bad[1] == 0 : c->lv[level].complete && bad[1] == 0;
   return VI_OK;
 }
 
@@ -851,6 +864,19 @@ struct vi_batch {
 };
 
 namespace {
+
+// the clip leaves the batch once the batch's queued work is done, and gets
+// its own stream back
+void batch_detach(vi_batch* b, vi_ctx* c) {
+  (void)hipStreamSynchronize(b->st);
+  for (size_t i = 0; i < b->members.size(); ++i)
+    if (b->members[i] == c) {
+      b->members.erase(b->members.begin() + (long)i);
+      break;
+    }
+  c->st = c->own_st;
+  c->batch = nullptr;
+}
 
 void batch_free(vi_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -1218,6 +1244,12 @@ vi_status vi_batch_create(vi_batch** out, const vi_tune* tune, void* hip_stream)
 void vi_batch_destroy(vi_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->st);
+  // members outlive the batch: they go back to their own streams
+  for (vi_ctx* c : b->members) {
+    c->st = c->own_st;
+    c->batch = nullptr;
+  }
+  b->members.clear();
   batch_free(b);
   if (b->own_stream) (void)hipStreamDestroy(b->st);
   delete b;
@@ -1225,8 +1257,8 @@ void vi_batch_destroy(vi_batch* b) {
 
 vi_status vi_batch_add(vi_batch* b, vi_ctx* c) {
   if (!b || !c) return fail(VI_E_INVAL, "null argument");
-  for (vi_ctx* m : b->members)
-    if (m == c) return fail(VI_E_INVAL, "the clip is already in the batch");
+  if (c->batch == b) return fail(VI_E_INVAL, "the clip is already in the batch");
+  if (c->batch) return fail(VI_E_INVAL, "the clip is in another batch");
   if (c->prm.n_jf < 1) return fail(VI_E_INVAL, "batched clips need at least one propagation step");
   if (b->have_sched && !same_schedule(b->sched, c->prm))
     return fail(VI_E_INVAL, "all clips of a batch share pm_iters and jf_steps");
@@ -1238,20 +1270,18 @@ vi_status vi_batch_add(vi_batch* b, vi_ctx* c) {
   }
   // the clip's work is ordered on the batch's stream from now on
   (void)hipStreamSynchronize(c->st);
+  c->own_st = c->st;
   c->st = b->st;
+  c->batch = b;
   b->members.push_back(c);
   return VI_OK;
 }
 
 vi_status vi_batch_remove(vi_batch* b, vi_ctx* c) {
   if (!b || !c) return fail(VI_E_INVAL, "null argument");
-  for (size_t i = 0; i < b->members.size(); ++i)
-    if (b->members[i] == c) {
-      (void)hipStreamSynchronize(b->st);
-      b->members.erase(b->members.begin() + (long)i);
-      return VI_OK;
-    }
-  return fail(VI_E_INVAL, "the clip is not in the batch");
+  if (c->batch != b) return fail(VI_E_INVAL, "the clip is not in the batch");
+  batch_detach(b, c);
+  return VI_OK;
 }
 
 int32_t vi_batch_size(const vi_batch* b) { return b ? (int32_t)b->members.size() : 0; }

@@ -169,7 +169,8 @@ void launch_erode3(hipStream_t st, const uint8_t* Hp, uint8_t* E, uint8_t* bd, i
 void launch_get_state(hipStream_t st, DevLevel L, uint8_t* rgbt, int32_t* cand, int32_t* dist,
                       uint8_t* nvox);
 void launch_set_state(hipStream_t st, DevLevel L, const uint8_t* rgbt, const int32_t* cand,
-                      const int32_t* dist, const uint8_t* nvox, unsigned long long* bad);
+                      const int32_t* dist, const uint8_t* nvox, unsigned long long* bad,
+                      int write);
 void launch_out_rgb(hipStream_t st, DevLevel L0, uint8_t* out);
 
 // batched launches over every job's chunks: persistent (grid = `grid`

@@ -1313,11 +1313,24 @@ __global__ void k_get_state(DevLevel L, uint8_t* rgbt, int32_t* cand, int32_t* d
 
 // bad[0]: cand outside [-1, V); bad[1]: target without a source match or
 // with a zero voxel count
+// write = 0 only counts the entries vi_set_state rejects (bad[0]: a match
+// outside [-1, V)) and those that leave the map incomplete (bad[1]); write = 1
+// also stores the state.  The host validates before writing, so a rejected
+// call leaves the level as it was.
 __global__ void k_set_state(DevLevel L, const uint8_t* rgbt, const int32_t* cand,
-                            const int32_t* dist, const uint8_t* nvox, unsigned long long* bad) {
+                            const int32_t* dist, const uint8_t* nvox, unsigned long long* bad,
+                            int write) {
   const int32_t i = blockIdx.x * kBlock + threadIdx.x;
   int b0 = 0, b1 = 0;
-  if (i < L.V) {
+  if (i < L.V && !write) {
+    const bool tg = L.htil[i] != 0;
+    if (cand) {
+      const int32_t c = cand[i];
+      if (c < -1 || c >= L.V) b0 = 1;
+      else if (tg && (c < 0 || !L.dsrc[c])) b1 = 1;
+    }
+    if (nvox && tg && nvox[i] == 0) b1 = 1;
+  } else if (i < L.V) {
     if (rgbt && L.hole[i]) {
       const uint8_t* s = rgbt + 5 * (size_t)i;
       L.vox[i] = make_uint2((uint32_t)s[0] | ((uint32_t)s[1] << 8) | ((uint32_t)s[2] << 16),
@@ -1325,18 +1338,10 @@ __global__ void k_set_state(DevLevel L, const uint8_t* rgbt, const int32_t* cand
     }
     const bool tg = L.htil[i] != 0;
     int2 nn = L.nnf0[i];
-    if (cand) {
-      const int32_t c = cand[i];
-      if (c < -1 || c >= L.V) b0 = 1;
-      nn.x = tg ? c : -1;
-      if (tg && (c < 0 || c >= L.V || !L.dsrc[c])) b1 = 1;
-    }
+    if (cand) nn.x = tg ? cand[i] : -1;
     if (dist) nn.y = tg ? dist[i] : -1;
     L.nnf0[i] = nn;
-    if (nvox) {
-      L.nvox[i] = tg ? nvox[i] : 0;
-      if (tg && nvox[i] == 0) b1 = 1;
-    }
+    if (nvox) L.nvox[i] = tg ? nvox[i] : 0;
   }
   unsigned long long s0 = wave_sum_u64((unsigned long long)b0);
   unsigned long long s1 = wave_sum_u64((unsigned long long)b1);
@@ -1463,8 +1468,9 @@ void launch_get_state(hipStream_t st, DevLevel L, uint8_t* rgbt, int32_t* cand, 
 }
 
 void launch_set_state(hipStream_t st, DevLevel L, const uint8_t* rgbt, const int32_t* cand,
-                      const int32_t* dist, const uint8_t* nvox, unsigned long long* bad) {
-  k_set_state<<<grid_for(L.V), kBlock, 0, st>>>(L, rgbt, cand, dist, nvox, bad);
+                      const int32_t* dist, const uint8_t* nvox, unsigned long long* bad,
+                      int write) {
+  k_set_state<<<grid_for(L.V), kBlock, 0, st>>>(L, rgbt, cand, dist, nvox, bad, write);
 }
 
 void launch_out_rgb(hipStream_t st, DevLevel L0, uint8_t* out) {

@@ -158,3 +158,23 @@ def test_batch_errors(vi):
     assert e.value.status == -4
     b.remove(g)
     assert len(b) == 0
+
+
+def test_clips_outlive_their_batch(vi, references):
+    # a clip removed mid-run, and a member of a batch destroyed under it,
+    # get their own streams back and keep working
+    print("[case] clips outlive their batch", flush=True)
+    c, kw = clips()[1]
+    b = vi.Batch(tune=(128, 2))
+    g = vi.Clip(dev(c.occluded_input()), dev(c.mask), **kw)
+    b.add(g)
+    b.step()
+    b.step()
+    b.remove(g)
+    b.close()
+    b2 = vi.Batch(tune=(256, 0))
+    b2.add(g)
+    b2.run()
+    b2.close()  # g is still a member here
+    assert np.array_equal(g.output().cpu().numpy(), references[1])
+    g.close()

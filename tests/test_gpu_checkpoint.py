@@ -67,3 +67,36 @@ def test_resume_from_a_checkpoint(vi, mode):
     resumed = finish(vi, g, 1)
     g.close()
     assert np.array_equal(resumed, ref)
+
+
+def test_rejected_set_state_keeps_the_level(vi):
+    # a match outside [-1, V) is refused before anything is written, so the
+    # level keeps its searched state; a match inside the volume that is not
+    # a source leaves the level incomplete, and the reconstruction refuses
+    # it on the host (no kernel reads through that match)
+    print("[case] rejected set_state", flush=True)
+    clip = synth.small(62, 50, 40, 9, levels=1, frac=0.05)
+    g = vi.Clip(dev(clip.occluded_input()), dev(clip.mask), levels=1, seed=4, recon_mode=1)
+    g.onion_init()
+    g.nnf_search(0, 1)
+    before = [host(t).copy() for t in g.get_state(0)]
+    cand = before[1]
+    tgt = np.flatnonzero(cand.ravel() >= 0)
+    assert tgt.size > 0
+    bad = cand.copy()
+    bad.ravel()[tgt[tgt.size // 2]] = cand.size  # one past the last voxel
+    with pytest.raises(vi.ViError) as e:
+        g.set_state(0, cand=bad)
+    assert e.value.status == -1
+    after = [host(t) for t in g.get_state(0)]
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
+    g.reconstruct(0, vi.MEAN, want_out=False)  # still complete
+    _, dsrc, _ = g.sets(0)
+    nonsrc = cand.copy()
+    nonsrc.ravel()[tgt[0]] = int(np.flatnonzero(host(dsrc).ravel() == 0)[0])
+    g.set_state(0, cand=nonsrc)
+    with pytest.raises(vi.ViError) as e:
+        g.reconstruct(0, vi.MEAN, want_out=False)
+    assert e.value.status == -4
+    g.close()
