@@ -105,6 +105,8 @@ static int64_t draw_below(uint64_t w, int64_t n) {
   return (int64_t)(((w >> 32) * (uint64_t)n) >> 32);
 }
 
+int64_t vio_draw_below(uint64_t w, int64_t n) { return n > 0 ? draw_below(w, n) : -1; }
+
 /* ------------------------------------------------------------------------ */
 /* helpers                                                                  */
 /* ------------------------------------------------------------------------ */
@@ -459,11 +461,55 @@ int64_t vio_patch_ssd(const vio_ctx* ctx, int32_t level, int64_t p, int64_t c,
 /*   whose patch fits the volume), r_max = largest dimension of the level;  */
 /*   adopted if it is in D~ and strictly better.                            */
 /* ------------------------------------------------------------------------ */
+/* Random-search radius of PatchMatch iteration k (Eq. (3.1)):
+ * floor(r_max rho^k), rho^k formed by k successive multiplications. */
+static int64_t rs_radius(const vio_params* P, int32_t r_max, int k) {
+  double r = (double)r_max;
+  for (int i = 0; i < k; ++i) r *= P->rho;
+  return (int64_t)floor(r);
+}
+
+/* The random-search candidate of target p around its match c0 (Eq. (3.1)):
+ * per axis the window [c0 - R, c0 + R] clipped to the centres whose whole
+ * patch lies in the volume, and one uniform integer drawn in it from the
+ * high half of Philox word x, y, t respectively. */
+static int64_t rs_candidate(const vio_ctx* ctx, int32_t level, int64_t p, int64_t c0lin,
+                            int64_t R, uint64_t step, int k) {
+  const level_t* L = &ctx->lv[level];
+  const vio_params* P = &ctx->prm;
+  int32_t c0x, c0y, c0t;
+  unlin(L, c0lin, &c0x, &c0y, &c0t);
+  const int64_t c0[3] = {c0x, c0y, c0t};
+  const int64_t dim[3] = {L->W, L->H, L->T};
+  const int64_t hh[3] = {P->patch[0] / 2, P->patch[1] / 2, P->patch[2] / 2};
+  const uint64_t key[2] = {P->seed, 0};
+  uint64_t ctr[4] = {(uint64_t)p, step, (uint64_t)k, ((uint64_t)level << 8) | 0u};
+  uint64_t w[4];
+  vio_philox4x64_10(ctr, key, w);
+  int64_t c[3];
+  for (int a = 0; a < 3; ++a) {
+    const int64_t lo = c0[a] - R > hh[a] ? c0[a] - R : hh[a];
+    const int64_t hi = c0[a] + R < dim[a] - 1 - hh[a] ? c0[a] + R : dim[a] - 1 - hh[a];
+    c[a] = lo + draw_below(w[a], hi - lo + 1);
+  }
+  return lin(L, c[0], c[1], c[2]);
+}
+
+int64_t vio_rs_candidate(const vio_ctx* ctx, int32_t level, int64_t p, int64_t c0, int32_t k,
+                         uint64_t step) {
+  if (!ctx || level < 0 || level >= ctx->L || k < 1) return -1;
+  const level_t* L = &ctx->lv[level];
+  if (p < 0 || p >= L->V || c0 < 0 || c0 >= L->V || !L->dsrc[c0]) return -1;
+  const int32_t r_max = L->W > L->H ? (L->W > L->T ? L->W : L->T) : (L->H > L->T ? L->H : L->T);
+  const int64_t R = rs_radius(&ctx->prm, r_max, k);
+  if (R < 1) return -1;
+  return rs_candidate(ctx, level, p, c0, R, step, k);
+}
+
 static void search(vio_ctx* ctx, int32_t level, const uint8_t* tmask, const uint8_t* cmask,
                    uint64_t step) {
   level_t* L = &ctx->lv[level];
   const vio_params* P = &ctx->prm;
-  const int hx = P->patch[0] / 2, hy = P->patch[1] / 2, ht = P->patch[2] / 2;
   const int64_t V = L->V;
   /* target list in ascending order */
   int64_t nS = 0;
@@ -533,30 +579,12 @@ static void search(vio_ctx* ctx, int32_t level, const uint8_t* tmask, const uint
       memcpy(L->dist, ndist, sizeof(int32_t) * (size_t)V);
     }
     /* random search, Eq. (3.1) */
-    double r = (double)r_max;
-    for (int i = 0; i < k; ++i) r *= P->rho;
-    const int64_t R = (int64_t)floor(r);
+    const int64_t R = rs_radius(P, r_max, k);
     if (R < 1) continue;
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t j = 0; j < nS; ++j) {
       int64_t p = S[j];
-      int32_t c0x, c0y, c0t;
-      unlin(L, L->cand[p], &c0x, &c0y, &c0t);
-      int64_t lo[3], hi[3];
-      const int32_t c0[3] = {c0x, c0y, c0t};
-      const int32_t dim[3] = {L->W, L->H, L->T};
-      const int32_t hh[3] = {hx, hy, ht};
-      for (int a = 0; a < 3; ++a) {
-        lo[a] = c0[a] - R > hh[a] ? c0[a] - R : hh[a];
-        hi[a] = c0[a] + R < dim[a] - 1 - hh[a] ? c0[a] + R : dim[a] - 1 - hh[a];
-      }
-      uint64_t ctr[4] = {(uint64_t)p, step, (uint64_t)k, ((uint64_t)level << 8) | 0u};
-      uint64_t w[4];
-      vio_philox4x64_10(ctr, key, w);
-      int64_t cx = lo[0] + draw_below(w[0], hi[0] - lo[0] + 1);
-      int64_t cy = lo[1] + draw_below(w[1], hi[1] - lo[1] + 1);
-      int64_t ct = lo[2] + draw_below(w[2], hi[2] - lo[2] + 1);
-      int64_t c = lin(L, cx, cy, ct);
+      int64_t c = rs_candidate(ctx, level, p, L->cand[p], R, step, k);
       if (!L->dsrc[c]) continue;
       int64_t d = ssd(ctx, L, p, c, cmask, NULL);
       if (d < L->dist[p]) {
@@ -745,58 +773,85 @@ int vio_inpaint_level(vio_ctx* ctx, int32_t level, int32_t* iters_run) {
 /* the partial distance over voxels outside H' (Eq. (3.10)), and the layer  */
 /* is reconstructed from those targets only (Eq. (3.11)).                   */
 /* ------------------------------------------------------------------------ */
-int vio_onion_init(vio_ctx* ctx, int32_t* layers_run) {
-  if (!ctx) return VIO_E_INVAL;
+int vio_onion_layer(vio_ctx* ctx, uint8_t* Hp, int32_t layer, uint8_t* bd_out, uint8_t* S_out,
+                    float* out_f, int64_t* n_layer) {
+  if (!ctx || !Hp || layer < 0) return VIO_E_INVAL;
   const int32_t level = ctx->L - 1;
   level_t* L = &ctx->lv[level];
   const int hx = ctx->prm.patch[0] / 2, hy = ctx->prm.patch[1] / 2, ht = ctx->prm.patch[2] / 2;
   const size_t V = (size_t)L->V;
-  uint8_t* Hp = (uint8_t*)malloc(V);
+  if (layer == 0) /* the peel starts from an empty shift map */
+    for (size_t i = 0; i < V; ++i) { L->cand[i] = -1; L->dist[i] = -1; L->nvox[i] = 0; }
   uint8_t* E = (uint8_t*)malloc(V);
   uint8_t* bd = (uint8_t*)malloc(V);
   uint8_t* S = (uint8_t*)malloc(V);
   uint8_t* M = (uint8_t*)malloc(V);
-  memcpy(Hp, L->hole, V);
-  for (size_t i = 0; i < V; ++i) { L->cand[i] = -1; L->dist[i] = -1; L->nvox[i] = 0; }
+  if (!E || !bd || !S || !M) {
+    free(E); free(bd); free(S); free(M);
+    return VIO_E_NOMEM;
+  }
+  /* E = erosion of H' by the 3x3x3 cube, outside the volume counting as
+   * occluded; the layer is H' minus E */
+  int64_t nb = 0;
+  for (int32_t t = 0; t < L->T; ++t)
+    for (int32_t y = 0; y < L->H; ++y)
+      for (int32_t x = 0; x < L->W; ++x) {
+        int all = 1;
+        for (int dt = -1; dt <= 1; ++dt)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx)
+              if (inside(L, x + dx, y + dy, t + dt) && !Hp[lin(L, x + dx, y + dy, t + dt)])
+                all = 0;
+        int64_t i = lin(L, x, y, t);
+        E[i] = (uint8_t)(Hp[i] && all);
+        bd[i] = (uint8_t)(Hp[i] && !E[i]);
+        nb += bd[i];
+      }
+  /* targets: voxels outside H' whose patch touches the layer */
+  for (int32_t t = 0; t < L->T; ++t)
+    for (int32_t y = 0; y < L->H; ++y)
+      for (int32_t x = 0; x < L->W; ++x) {
+        int64_t i = lin(L, x, y, t);
+        int near = 0;
+        for (int dt = -ht; dt <= ht; ++dt)
+          for (int dy = -hy; dy <= hy; ++dy)
+            for (int dx = -hx; dx <= hx; ++dx)
+              if (inside(L, x + dx, y + dy, t + dt) && bd[lin(L, x + dx, y + dy, t + dt)])
+                near = 1;
+        S[i] = (uint8_t)(near && !Hp[i]);
+        M[i] = (uint8_t)!Hp[i];
+      }
+  if (nb > 0) {
+    search(ctx, level, S, M, (1ULL << 32) + (uint64_t)layer);
+    reconstruct(ctx, L, bd, M, ctx->prm.recon_mode, out_f);
+  }
+  L->searched = 0; /* the inner layers' targets may still be unmatched */
+  if (bd_out) memcpy(bd_out, bd, V);
+  if (S_out) memcpy(S_out, S, V);
+  memcpy(Hp, E, V);
+  free(E); free(bd); free(S); free(M);
+  if (n_layer) *n_layer = nb;
+  return VIO_OK;
+}
+
+int vio_onion_init(vio_ctx* ctx, int32_t* layers_run) {
+  if (!ctx) return VIO_E_INVAL;
+  level_t* L = &ctx->lv[ctx->L - 1];
+  uint8_t* Hp = (uint8_t*)malloc((size_t)L->V);
+  if (!Hp) return VIO_E_NOMEM;
+  memcpy(Hp, L->hole, (size_t)L->V);
   int32_t layer = 0;
   for (;;) {
-    int64_t any = 0;
-    for (size_t i = 0; i < V; ++i) any += Hp[i];
-    if (!any) break;
-    for (int32_t t = 0; t < L->T; ++t)
-      for (int32_t y = 0; y < L->H; ++y)
-        for (int32_t x = 0; x < L->W; ++x) {
-          int all = 1;
-          for (int dt = -1; dt <= 1; ++dt)
-            for (int dy = -1; dy <= 1; ++dy)
-              for (int dx = -1; dx <= 1; ++dx)
-                if (inside(L, x + dx, y + dy, t + dt) && !Hp[lin(L, x + dx, y + dy, t + dt)])
-                  all = 0;
-          int64_t i = lin(L, x, y, t);
-          E[i] = (uint8_t)(Hp[i] && all);
-          bd[i] = (uint8_t)(Hp[i] && !E[i]);
-        }
-    for (int32_t t = 0; t < L->T; ++t)
-      for (int32_t y = 0; y < L->H; ++y)
-        for (int32_t x = 0; x < L->W; ++x) {
-          int64_t i = lin(L, x, y, t);
-          int near = 0;
-          for (int dt = -ht; dt <= ht; ++dt)
-            for (int dy = -hy; dy <= hy; ++dy)
-              for (int dx = -hx; dx <= hx; ++dx)
-                if (inside(L, x + dx, y + dy, t + dt) && bd[lin(L, x + dx, y + dy, t + dt)])
-                  near = 1;
-          S[i] = (uint8_t)(near && !Hp[i]);
-          M[i] = (uint8_t)!Hp[i];
-        }
-    search(ctx, level, S, M, (1ULL << 32) + (uint64_t)layer);
-    reconstruct(ctx, L, bd, M, ctx->prm.recon_mode, NULL);
-    memcpy(Hp, E, V);
+    int64_t nb = 0;
+    int st = vio_onion_layer(ctx, Hp, layer, NULL, NULL, NULL, &nb);
+    if (st) {
+      free(Hp);
+      return st;
+    }
+    if (nb == 0) break; /* H' is empty */
     ++layer;
   }
-  free(Hp); free(E); free(bd); free(S); free(M);
-  /* the innermost layer's targets may still be unmatched */
-  L->searched = 0;
+  free(Hp);
   if (layers_run) *layers_run = layer;
   return VIO_OK;
 }

@@ -84,6 +84,14 @@ int64_t vio_patch_ssd(const vio_ctx* ctx, int32_t level, int64_t p, int64_t c,
 
 /* Philox4x64-10 block: out = Philox(counter, key). */
 void vio_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+/* The uniform integer in [0, n) that a 64-bit random word maps to: the high
+ * 32 bits times n, divided by 2^32 (-1 for n <= 0). */
+int64_t vio_draw_below(uint64_t w, int64_t n);
+/* The random-search candidate (linear index) the search draws for target p
+ * around its match c0 (a source) in PatchMatch iteration k >= 1 with random
+ * step `step` (Eq. (3.1)); -1 for bad arguments or a radius below 1. */
+int64_t vio_rs_candidate(const vio_ctx* ctx, int32_t level, int64_t p, int64_t c0, int32_t k,
+                         uint64_t step);
 
 /* ANN search (Alg. "ANN search with 3D PatchMatch", redesigned as
  * synchronous propagation) over the target set H~^level with the full
@@ -103,8 +111,21 @@ int vio_reconstruct(vio_ctx* ctx, int32_t level, int32_t mode, float* out_f, int
  * algorithm", inner while loop); iters_run receives the number of
  * iterations. */
 int vio_inpaint_level(vio_ctx* ctx, int32_t level, int32_t* iters_run);
-/* Onion-peel initialisation at the coarsest level (Sec. 3.5). */
+/* Onion-peel initialisation at the coarsest level (Sec. 3.5, Alg. 3). */
 int vio_onion_init(vio_ctx* ctx, int32_t* layers_run);
+/* One layer of the onion peel at the coarsest level.  Hp [V] holds the
+ * current occlusion H' on entry and its erosion by the 3x3x3 cube (outside
+ * the volume counted as occluded) on return.  The layer is H' minus that
+ * erosion; its targets are the voxels outside H' whose patch touches it;
+ * they are searched with the partial distance over voxels outside H'
+ * (Eq. (3.10)) and the layer is reconstructed from those contributors only
+ * (Eq. (3.11)).  layer keys the random numbers (step 2^32 + layer); layer 0
+ * first empties the level's shift map.  bd_out / S_out [V] (or NULL) receive
+ * the layer and its targets, out_f [|layer|][5] (or NULL) the reconstructed
+ * values in [0,1] in ascending linear order, n_layer the layer's size (0:
+ * H' was empty and nothing was done). */
+int vio_onion_layer(vio_ctx* ctx, uint8_t* Hp, int32_t layer, uint8_t* bd_out, uint8_t* S_out,
+                    float* out_f, int64_t* n_layer);
 /* Level transition level+1 -> level: nearest-neighbour upsampling of the
  * shift map, then reconstruction of the finer hole (Sec. 3.6). */
 int vio_transition(vio_ctx* ctx, int32_t level);

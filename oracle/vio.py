@@ -57,6 +57,12 @@ def lib():
         L.vio_patch_ssd.restype = C.c_int64
         L.vio_philox4x64_10.argtypes = [P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
         L.vio_philox4x64_10.restype = None
+        L.vio_draw_below.argtypes = [C.c_uint64, C.c_int64]
+        L.vio_draw_below.restype = C.c_int64
+        L.vio_rs_candidate.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_int32,
+                                       C.c_uint64]
+        L.vio_rs_candidate.restype = C.c_int64
+        L.vio_onion_layer.argtypes = [C.c_void_p, u8p, C.c_int32, u8p, u8p, f32p, i64p]
         L.vio_nnf_search.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
         L.vio_nnf_search_set.argtypes = [C.c_void_p, C.c_int32, u8p, u8p, C.c_uint64]
         L.vio_reconstruct.argtypes = [C.c_void_p, C.c_int32, C.c_int32, f32p, i64p]
@@ -84,6 +90,10 @@ def philox4x64_10(ctr, key):
     o = np.zeros(4, np.uint64)
     lib().vio_philox4x64_10(_ptr(c, C.c_uint64), _ptr(k, C.c_uint64), _ptr(o, C.c_uint64))
     return o
+
+
+def draw_below(w, n):
+    return int(lib().vio_draw_below(C.c_uint64(int(w)), int(n)))
 
 
 def default_params(**kw) -> Params:
@@ -217,6 +227,24 @@ class Oracle:
         k = C.c_int32(0)
         _check("vio_onion_init", lib().vio_onion_init(self.h, C.byref(k)))
         return int(k.value)
+
+    def onion_layer(self, Hp, layer):
+        """One onion-peel layer: returns (erosion of Hp, layer mask, target
+        mask, reconstructed values [|layer|][5] in [0,1])."""
+        E = np.ascontiguousarray(Hp, np.uint8).copy()
+        bd = np.zeros_like(E)
+        S = np.zeros_like(E)
+        n = C.c_int64(0)
+        nb = int(np.count_nonzero(Hp))
+        out = np.zeros((max(nb, 1), 5), np.float32)
+        _check("vio_onion_layer", lib().vio_onion_layer(
+            self.h, _ptr(E, C.c_uint8), layer, _ptr(bd, C.c_uint8), _ptr(S, C.c_uint8),
+            _ptr(out, C.c_float), C.byref(n)))
+        return E, bd, S, out[:int(n.value)]
+
+    def rs_candidate(self, level, p, c0, k, step=0):
+        return int(lib().vio_rs_candidate(self.h, level, int(p), int(c0), int(k),
+                                          C.c_uint64(int(step))))
 
     def transition(self, level):
         _check("vio_transition", lib().vio_transition(self.h, level))
