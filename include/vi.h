@@ -127,6 +127,25 @@ vi_status vi_inpaint_level(vi_ctx* ctx, int32_t level, int32_t* em_iters_run);
  * (3.9)-(3.11)).  layers_run (host) or NULL.  Syncs once per layer. */
 vi_status vi_onion_init(vi_ctx* ctx, int32_t* layers_run);
 
+/* One layer of the onion peel (Sec. 3.5, Alg. 3), as vi_onion_init runs it,
+ * for driving and testing the peel a layer at a time.
+ *   Hp      (dev) [T][H_c][W_c] bytes of the coarsest level: the current
+ *           occlusion H' on entry (nonzero = occluded), its erosion by the
+ *           3x3x3 cube (outside the volume counted as occluded) on return.
+ *   layer   keys the random numbers (step 2^32 + layer); layer 0 first
+ *           empties the level's shift map.
+ *   out_f   (dev) [|layer|][5] float in [0,1] receiving the reconstructed
+ *           layer H' minus its erosion, in ascending linear order, or NULL.
+ *   n_layer (host) receives the layer's size (0: H' was empty, nothing was
+ *           searched), or NULL.
+ * The layer's targets (voxels outside H' whose patch touches the layer) are
+ * searched with the distance over the voxels outside H' (Eq. (3.10)), and
+ * the layer is rebuilt from those contributors only (Eq. (3.11)).  Leaves the
+ * level incomplete (vi_reconstruct refuses it until a full search).  Syncs.
+ * Errors: VI_E_INVAL (null Hp, layer < 0), VI_E_STATE (clip in a batch). */
+vi_status vi_onion_layer(vi_ctx* ctx, uint8_t* Hp, int32_t layer, float* out_f,
+                         int64_t* n_layer);
+
 /* Level transition level+1 -> level (Sec. 3.6): nearest-neighbour upsampling
  * of the shift map and reconstruction of H^level with recon_mode. */
 vi_status vi_transition(vi_ctx* ctx, int32_t level);

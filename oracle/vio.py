@@ -147,7 +147,10 @@ class Oracle:
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown
+            pass
 
     @property
     def levels(self):

@@ -365,34 +365,70 @@ vi_status inpaint_level(vi_ctx* c, int32_t level, int32_t* iters) {
   return VI_OK;
 }
 
-// scratch of the onion peel, empty shift maps, H' = the coarsest hole
-vi_status onion_prepare(vi_ctx* c) {
-  c->lv[c->L - 1].recon_ok = false;  // the shift maps are emptied below
-  const vi::DevLevel& d = c->lv[c->L - 1].d;
-  const size_t V = (size_t)d.V;
-  if (!c->o_Hp) {
-    // exclusion masks: padded for the 8-byte row loads of the distance
-    VI_TRY(dalloc(c, &c->o_Hp, V + 2 * vi::kMarkPad));
-    VI_TRY(dalloc(c, &c->o_E, V + 2 * vi::kMarkPad));
-    c->o_Hp += vi::kMarkPad;
-    c->o_E += vi::kMarkPad;
-    VI_TRY(dalloc(c, &c->o_bd, V));
-    VI_TRY(dalloc(c, &c->o_S, V));
-    VI_TRY(dalloc(c, &c->o_t1, V));
-    VI_TRY(dalloc(c, &c->o_t2, V));
-    VI_TRY(dalloc(c, &c->o_tl, V));
-    VI_TRY(dalloc(c, &c->o_pl, V));
-  }
-  vi::launch_fill_nnf(c->st, d.nnf0, d.nvox, d.V);
-  vi::launch_fill_nnf(c->st, d.nnf1, nullptr, d.V);
-  VI_HIP(hipMemcpyAsync(c->o_Hp, d.hole, V, hipMemcpyDeviceToDevice, c->st));
+// scratch of the onion peel (allocated once per context)
+vi_status onion_buffers(vi_ctx* c) {
+  if (c->o_Hp) return VI_OK;
+  const size_t V = (size_t)c->lv[c->L - 1].d.V;
+  // exclusion masks: padded for the 8-byte row loads of the distance
+  VI_TRY(dalloc(c, &c->o_Hp, V + 2 * vi::kMarkPad));
+  VI_TRY(dalloc(c, &c->o_E, V + 2 * vi::kMarkPad));
+  c->o_Hp += vi::kMarkPad;
+  c->o_E += vi::kMarkPad;
+  VI_TRY(dalloc(c, &c->o_bd, V));
+  VI_TRY(dalloc(c, &c->o_S, V));
+  VI_TRY(dalloc(c, &c->o_t1, V));
+  VI_TRY(dalloc(c, &c->o_t2, V));
+  VI_TRY(dalloc(c, &c->o_tl, V));
+  VI_TRY(dalloc(c, &c->o_pl, V));
+  return VI_OK;
+}
+
+// the peel starts from empty shift maps at the coarsest level
+vi_status onion_empty_maps(vi_ctx* c) {
+  Level& lv = c->lv[c->L - 1];
+  lv.recon_ok = false;
+  vi::launch_fill_nnf(c->st, lv.d.nnf0, lv.d.nvox, lv.d.V);
+  vi::launch_fill_nnf(c->st, lv.d.nnf1, nullptr, lv.d.V);
   return launched("onion set-up");
+}
+
+// One layer of Alg. 3 at the coarsest level: E = erosion of H' (Hp), the
+// layer bd = H' \ E and its targets S = dilate(bd) \ H'; search of S with
+// the distance over voxels outside H', reconstruction of bd from the
+// contributors outside H'.  *nb receives |bd| (0: H' is empty, nothing
+// searched).  Syncs.
+vi_status onion_step(vi_ctx* c, const uint8_t* Hp, uint8_t* E, int32_t layer, float* out_f,
+                     int32_t* nb) {
+  const int32_t level = c->L - 1;
+  const vi::DevLevel& d = c->lv[level].d;
+  const int r = prof_begin(c, VI_K_OTHER);
+  vi::launch_erode3(c->st, Hp, E, c->o_bd, d.W, d.H, d.T);
+  vi::launch_dilate5(c->st, c->o_bd, c->o_S, c->o_t1, c->o_t2, d.W, d.H, d.T, Hp);
+  prof_end(c, r, VI_K_OTHER, level, d.V);
+  VI_TRY(launched("onion layer"));
+  VI_HIP(vi::compact(c->st, c->o_bd, d.V, c->o_pl, c->d_count, c->ctemp, c->ctemp_bytes));
+  VI_HIP(vi::compact(c->st, c->o_S, d.V, c->o_tl, c->d_count + 1, c->ctemp, c->ctemp_bytes));
+  int32_t cnt[2] = {0, 0};
+  VI_HIP(hipMemcpyAsync(cnt, c->d_count, sizeof(cnt), hipMemcpyDeviceToHost, c->st));
+  VI_TRY(sync(c));
+  *nb = cnt[0];
+  if (cnt[0] == 0) return VI_OK;
+  VI_TRY(search(c, level, c->o_tl, cnt[1], c->o_S, Hp, (uint64_t(1) << 32) + (uint64_t)layer));
+  return recon(c, level, c->o_pl, cnt[0], Hp, c->prm.recon_mode, out_f, nullptr);
+}
+
+// the start of a peel: scratch, empty shift maps, H' = the coarsest hole
+vi_status onion_prepare(vi_ctx* c) {
+  const vi::DevLevel& d = c->lv[c->L - 1].d;
+  VI_TRY(onion_buffers(c));
+  VI_TRY(onion_empty_maps(c));
+  VI_HIP(hipMemcpyAsync(c->o_Hp, d.hole, (size_t)d.V, hipMemcpyDeviceToDevice, c->st));
+  return VI_OK;
 }
 
 vi_status onion(vi_ctx* c, int32_t* layers_run) {
   const int32_t level = c->L - 1;
   Level& lv = c->lv[level];
-  const vi::DevLevel& d = lv.d;
   VI_TRY(onion_prepare(c));
   uint8_t* Hp = c->o_Hp;
   uint8_t* E = c->o_E;
@@ -403,19 +439,9 @@ vi_status onion(vi_ctx* c, int32_t* layers_run) {
   } kind_guard{c};
   c->kind_override = VI_K_ONION;
   for (;;) {
-    const int r = prof_begin(c, VI_K_OTHER);
-    vi::launch_erode3(c->st, Hp, E, c->o_bd, d.W, d.H, d.T);
-    vi::launch_dilate5(c->st, c->o_bd, c->o_S, c->o_t1, c->o_t2, d.W, d.H, d.T, Hp);
-    prof_end(c, r, VI_K_OTHER, level, d.V);
-    VI_TRY(launched("onion layer"));
-    VI_HIP(vi::compact(c->st, c->o_bd, d.V, c->o_pl, c->d_count, c->ctemp, c->ctemp_bytes));
-    VI_HIP(vi::compact(c->st, c->o_S, d.V, c->o_tl, c->d_count + 1, c->ctemp, c->ctemp_bytes));
-    int32_t cnt[2] = {0, 0};
-    VI_HIP(hipMemcpyAsync(cnt, c->d_count, sizeof(cnt), hipMemcpyDeviceToHost, c->st));
-    VI_TRY(sync(c));
-    if (cnt[0] == 0) break;  // no layer left: H' is empty
-    VI_TRY(search(c, level, c->o_tl, cnt[1], c->o_S, Hp, (uint64_t(1) << 32) + (uint64_t)layer));
-    VI_TRY(recon(c, level, c->o_pl, cnt[0], Hp, c->prm.recon_mode, nullptr, nullptr));
+    int32_t nb = 0;
+    VI_TRY(onion_step(c, Hp, E, layer, nullptr, &nb));
+    if (nb == 0) break;  // no layer left: H' is empty
     uint8_t* t = Hp;
     Hp = E;
     E = t;
@@ -667,6 +693,30 @@ vi_status vi_inpaint_level(vi_ctx* c, int32_t level, int32_t* em_iters_run) {
 vi_status vi_onion_init(vi_ctx* c, int32_t* layers_run) {
   if (!c) return fail(VI_E_INVAL, "null context");
   return onion(c, layers_run);
+}
+
+vi_status vi_onion_layer(vi_ctx* c, uint8_t* Hp, int32_t layer, float* out_f,
+                         int64_t* n_layer) {
+  if (!c || !Hp) return fail(VI_E_INVAL, "null argument");
+  if (layer < 0) return fail(VI_E_INVAL, "layer must be >= 0");
+  if (c->batch) return fail(VI_E_STATE, "the clip is in a batch");
+  Level& lv = c->lv[c->L - 1];
+  const size_t V = (size_t)lv.d.V;
+  VI_TRY(onion_buffers(c));
+  if (layer == 0) VI_TRY(onion_empty_maps(c));
+  lv.recon_ok = false;
+  VI_HIP(hipMemcpyAsync(c->o_Hp, Hp, V, hipMemcpyDeviceToDevice, c->st));
+  struct Kind {
+    vi_ctx* c;
+    ~Kind() { c->kind_override = -1; }
+  } kind_guard{c};
+  c->kind_override = VI_K_ONION;
+  int32_t nb = 0;
+  VI_TRY(onion_step(c, c->o_Hp, c->o_E, layer, out_f, &nb));
+  VI_HIP(hipMemcpyAsync(Hp, c->o_E, V, hipMemcpyDeviceToDevice, c->st));
+  lv.complete = false;  // the inner layers' targets may be unmatched
+  if (n_layer) *n_layer = nb;
+  return sync(c);
 }
 
 vi_status vi_transition(vi_ctx* c, int32_t level) {

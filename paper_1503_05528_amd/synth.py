@@ -14,8 +14,11 @@ All float fields are rounded half-up and clipped to 0..255.
 
 from __future__ import annotations
 
+import collections
+import concurrent.futures
 import dataclasses
 import math
+import os
 
 import numpy as np
 
@@ -86,16 +89,31 @@ def _background(rng, W, H, T, v_b, sigma, n_grat=6):
     g = rng.uniform(0.5, 1.0, (n_grat, 3))
     y, x = np.meshgrid(np.arange(H, dtype=np.float64), np.arange(W, dtype=np.float64),
                        indexing="ij")
-    frames = np.empty((T, H, W, 3), np.uint8)
-    for t in range(T):
+
+    def gratings(t):
         acc = np.full((H, W, 3), 128.0)
         for i in range(n_grat):
             s = np.sin(2 * np.pi * f[i] * (np.cos(th[i]) * (x + v_b * t) + np.sin(th[i]) * y)
                        + ph[i])
             acc += A[i] * s[..., None] * g[i][None, None, :]
-        if sigma > 0:
-            acc += rng.normal(0.0, sigma, (H, W, 3))
-        frames[t] = _u8(acc)
+        return acc
+
+    # the gratings of later frames are computed on worker threads (numpy
+    # releases the GIL) while the noise is drawn here, frame by frame in
+    # order, so the result does not depend on the thread count
+    frames = np.empty((T, H, W, 3), np.uint8)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+        pending = collections.deque()
+        nxt = 0
+        for t in range(T):
+            while nxt < T and len(pending) < 2 * workers:
+                pending.append(ex.submit(gratings, nxt))
+                nxt += 1
+            acc = pending.popleft().result()
+            if sigma > 0:
+                acc += rng.normal(0.0, sigma, (H, W, 3))
+            frames[t] = _u8(acc)
     return frames
 
 

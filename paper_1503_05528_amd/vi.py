@@ -55,6 +55,7 @@ SIGNATURES = {
     "vi_reconstruct": (_i32, [_vp, _i32, _i32, _vp, _vp]),
     "vi_inpaint_level": (_i32, [_vp, _i32, C.POINTER(_i32)]),
     "vi_onion_init": (_i32, [_vp, C.POINTER(_i32)]),
+    "vi_onion_layer": (_i32, [_vp, _vp, _i32, _vp, C.POINTER(C.c_int64)]),
     "vi_transition": (_i32, [_vp, _i32]),
     "vi_inpaint": (_i32, [_vp, _vp]),
     "vi_get_state": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp]),
@@ -277,6 +278,17 @@ class Clip:
         k = C.c_int32(0)
         _check("vi_onion_init", lib().vi_onion_init(self.h, C.byref(k)))
         return int(k.value)
+
+    def onion_layer(self, Hp, layer):
+        """One onion-peel layer: Hp (device uint8 [T][H][W] of the coarsest
+        level) is replaced by its erosion; returns the layer's reconstructed
+        values [|layer|][5] in [0,1]."""
+        nb = int(torch.count_nonzero(Hp))
+        out = self._new((max(nb, 1), 5), torch.float32)
+        n = C.c_int64(0)
+        _check("vi_onion_layer", lib().vi_onion_layer(self.h, _ptr(Hp), layer, _ptr(out),
+                                                      C.byref(n)))
+        return out[:int(n.value)]
 
     def transition(self, level):
         _check("vi_transition", lib().vi_transition(self.h, level))

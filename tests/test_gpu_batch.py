@@ -178,3 +178,94 @@ def test_clips_outlive_their_batch(vi, references):
     b2.close()  # g is still a member here
     assert np.array_equal(g.output().cpu().numpy(), references[1])
     g.close()
+
+
+# ---------------------------------------------------------------------------
+# batched members against the CPU oracle (Alg. 4, per member)
+# ---------------------------------------------------------------------------
+
+def reduced_draws(n=3, base_seed=1000):
+    """Clips drawn like the 64-clip batch (box or ellipse tube of 1-8 %,
+    2-3 levels) at sizes the oracle inpaints in seconds."""
+    out = []
+    for i in range(n):
+        rng = np.random.default_rng(base_seed + i)
+        W, H, T = int(rng.integers(40, 97)), int(rng.integers(34, 73)), int(rng.integers(8, 17))
+        L = int(rng.integers(2, 4))
+        kind = "box" if rng.uniform() < 0.5 else "ellipse"
+        c = synth.small(base_seed + i, W, H, T, frac=float(rng.uniform(0.01, 0.08)), levels=L,
+                        kind=kind)
+        out.append((c, dict(levels=L, seed=300 + i)))
+    return out
+
+
+@pytest.mark.parametrize("tune", [None, (128, 2), (256, 0)])
+def test_mean_batch_equals_oracle(vi, tune):
+    from oracle import vio
+    print(f"[case] MEAN batch vs oracle, tune={tune}", flush=True)
+    specs = [(c, dict(kw, recon_mode=1)) for c, kw in clips() + reduced_draws()]
+    b = vi.Batch(tune=tune)
+    members = []
+    for c, kw in specs:
+        g = vi.Clip(dev(c.occluded_input()), dev(c.mask), **kw)
+        b.add(g)
+        members.append(g)
+    b.run()
+    for i, ((c, kw), g) in enumerate(zip(specs, members)):
+        ref = vio.Oracle(c.occluded_input(), c.mask, **kw).inpaint()
+        assert np.array_equal(g.output().cpu().numpy(), ref), i
+        g.close()
+    b.close()
+
+
+@pytest.mark.parametrize("tune", [(128, 2), (256, 0)])
+def test_weighted_batch_step_teacher_forced(vi, tune):
+    # after the first step (onion peel and EM iteration 0 of every member),
+    # every member's coarsest level is forced to the oracle's state after the
+    # same two steps; the next batched step (EM iteration 1) must then match
+    # the oracle's search bit for bit and its weighted reconstruction within
+    # the tolerance
+    from oracle import vio
+    print(f"[case] weighted batch step vs oracle, tune={tune}", flush=True)
+    specs = [(c, dict(kw, recon_mode=0, em_tol=-1.0, em_max_iters=3))
+             for c, kw in clips() + reduced_draws()]
+    b = vi.Batch(tune=tune)
+    members, oracles = [], []
+    for c, kw in specs:
+        g = vi.Clip(dev(c.occluded_input()), dev(c.mask), **kw)
+        b.add(g)
+        members.append(g)
+        o = vio.Oracle(c.occluded_input(), c.mask, **kw)
+        o.onion_init()
+        lv = kw["levels"] - 1
+        o.nnf_search(lv, 0)
+        o.reconstruct(lv, vio.WEIGHTED, want_out=False)
+        oracles.append(o)
+    b.step()
+    for (c, kw), g, o in zip(specs, members, oracles):
+        lv = kw["levels"] - 1
+        g.set_state(lv, *o.get_state(lv))
+    b.step()
+    for i, ((c, kw), g, o) in enumerate(zip(specs, members, oracles)):
+        lv = kw["levels"] - 1
+        o.nnf_search(lv, 1)
+        _, oc, od, on = o.get_state(lv)
+        # the level's shift map is not touched after the search (a finished
+        # level only feeds the finer level's transition)
+        g_rgbt, gc, gd, gn = (t.cpu().numpy() for t in g.get_state(lv))
+        assert np.array_equal(oc, gc), f"member {i}: matches"
+        assert np.array_equal(od, gd), f"member {i}: distances"
+        assert np.array_equal(on, gn), f"member {i}: counts"
+        out, _ = o.reconstruct(lv, vio.WEIGHTED)
+        o_rgbt = o.get_state(lv)[0]
+        hole_idx = np.flatnonzero(o.sets(lv)[0].ravel())
+        a = o_rgbt.reshape(-1, 5)[hole_idx].astype(int)
+        bb = g_rgbt.reshape(-1, 5)[hole_idx].astype(int)
+        d = np.abs(a - bb)
+        assert d.max(initial=0) <= 1, i
+        if d.any():  # flips only at rounding boundaries of the oracle's value
+            v = out.astype(np.float64) * 255.0
+            assert (np.abs(v - np.floor(v) - 0.5)[d > 0] <= 1e-4 * 255.0 + 1e-3).all(), i
+    for g in members:
+        g.close()
+    b.close()

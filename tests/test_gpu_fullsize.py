@@ -1,17 +1,20 @@
-"""The SD workload at its full size (854x480 px x 100 frames, 4-level pyramid,
-5x5x5 patches), through the same entry points and launches that bench.py
-times, checked against the CPU oracle on what the oracle can afford at that
-size:
+"""The SD (854x480 px x 100 frames, 4 levels) and HD (1920x1080 px x 60
+frames, 5 levels) workloads at their full size, through the same entry points
+and launches that bench.py times, against the CPU oracle:
 
-* the finest level's sets (H, D~, H~) bit for bit;
-* every target's match is a source, and the stored distance and voxel count
-  of 2000 sampled targets equal the oracle's exact patch distance of the
-  stored match (vio_patch_ssd on the GPU's iterate);
-* no sampled target ends a search farther from its match than from the
-  match it came with (the search only replaces a match by a better one);
-* the weighted reconstruction of all 2.04M finest-level hole pixels from the
-  GPU's shift map, within 1e-4 on [0, 1];
+* every level's sets (H, D~, H~) bit for bit;
+* one ANN search of the finest level, teacher-forced from the same state on
+  both sides, compared over the whole shift map (matches, distances, voxel
+  counts) bit for bit;
+* the weighted reconstruction of every finest-level hole pixel from that
+  shift map, within 1e-4 on [0, 1];
 * a complete inpainting leaves every known pixel untouched.
+
+The finest level's state is produced the way the benchmark's runs reach it,
+on the oracle alone: a search of level 1 from random matches over a
+randomly filled hole, then the level transition (nearest-neighbour
+upsampling of the shift map and weighted reconstruction of the finest hole).
+The GPU's own transition from the same level-1 state is compared with it too.
 """
 import numpy as np
 import pytest
@@ -23,8 +26,9 @@ from paper_1503_05528_amd import synth
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-4
-# the configuration bench.py times
-PARAMS = dict(levels=4, em_tol=-1.0, em_max_iters=20, seed=1)
+# the configurations bench.py times
+PARAMS = {"sd": dict(levels=4, em_tol=-1.0, em_max_iters=20, seed=1),
+          "hd": dict(levels=5, em_tol=-1.0, em_max_iters=20, seed=1)}
 
 
 @pytest.fixture(scope="module")
@@ -32,11 +36,6 @@ def vi():
     from paper_1503_05528_amd import vi as _vi
     _vi.lib()
     return _vi
-
-
-@pytest.fixture(scope="module")
-def sd():
-    return synth.sd()
 
 
 def dev(a):
@@ -48,51 +47,84 @@ def host(t):
     return t.cpu().numpy()
 
 
-def test_sd_finest_level_search_and_reconstruction(vi, sd):
-    print("[case] sd 854x480x100 finest level, sampled", flush=True)
-    video, mask = sd.occluded_input(), sd.mask
-    g = vi.Clip(dev(video), dev(mask), **PARAMS)
-    g.onion_init()
-    for lvl in (3, 2, 1):
-        g.inpaint_level(lvl)
-        g.transition(lvl - 1)
-    _, cand_in, _, _ = (host(t) for t in g.get_state(0))
+def forced_level1(o, seed):
+    """A random fill of the level-1 hole (its matches start unset)."""
+    rgbt = o.get_state(1)[0]
+    hole = o.sets(1)[0].astype(bool)
+    rng = np.random.default_rng(seed)
+    rgbt[hole] = rng.integers(0, 256, (int(hole.sum()), 5), dtype=np.uint8)
+    return rgbt
+
+
+def check_full_level(vi, name, clip):
+    prm = PARAMS[name]
+    video, mask = clip.occluded_input(), clip.mask
+    print(f"[case] {name} {clip.shape}: oracle set-up", flush=True)
+    o = vio.Oracle(video, mask, **prm)
+    g = vi.Clip(dev(video), dev(mask), **prm)
+    for lv in range(prm["levels"]):
+        assert o.info(lv) == g.info(lv), lv
+        for a, b in zip(o.sets(lv), g.sets(lv)):
+            assert np.array_equal(a, host(b)), lv
+    print(f"[case] {name}: oracle search of level 1 and transition", flush=True)
+    o.set_state(1, rgbt=forced_level1(o, 5))
+    o.nnf_search(1, 0)
+    g.set_state(1, *o.get_state(1))
+    o.transition(0)
+    g.transition(0)
+    rgbt, cand, dist, nvox = o.get_state(0)
+    g_rgbt, g_cand, g_dist, g_nvox = (host(t) for t in g.get_state(0))
+    assert np.array_equal(cand, g_cand) and np.array_equal(dist, g_dist)
+    assert np.array_equal(nvox, g_nvox)
+    flips = np.abs(rgbt.astype(np.int16) - g_rgbt.astype(np.int16))
+    assert flips.max() <= 1 and (flips > 0).mean() < 1e-4, int((flips > 0).sum())
+    del g_rgbt, g_cand, g_dist, g_nvox, flips
+    g.set_state(0, rgbt=rgbt, cand=cand, dist=dist, nvox=nvox)
     g.nnf_search(0, em_iter=0)
-    rgbt, cand, dist, nvox = (host(t) for t in g.get_state(0))
-    sets_g = [host(t) for t in g.sets(0)]
-
-    o = vio.Oracle(video, mask, **PARAMS)
-    hole, dsrc, htil = o.sets(0)
-    for a, b in zip((hole, dsrc, htil), sets_g):
-        assert np.array_equal(a, b)
-    tg = np.flatnonzero(htil.ravel())
-    assert len(tg) == 2281480
-    c = cand.ravel()[tg]
-    assert (c >= 0).all() and dsrc.ravel()[c].all()
-
-    o.set_state(0, rgbt=rgbt)
-    rng = np.random.default_rng(7)
-    for p in rng.choice(tg, 2000, replace=False):
-        d, n = o.patch_ssd(0, p, cand.ravel()[p])
-        assert (d, n) == (int(dist.ravel()[p]), int(nvox.ravel()[p])), p
-        d_in, _ = o.patch_ssd(0, p, cand_in.ravel()[p])
-        assert int(dist.ravel()[p]) <= d_in, p
-
-    o.set_state(0, rgbt=rgbt, cand=cand, dist=dist, nvox=nvox)
-    ref, _ = o.reconstruct(0, vio.WEIGHTED)
+    _, gc, gd, gn = (host(t) for t in g.get_state(0))
+    print(f"[case] {name}: oracle search of the finest level", flush=True)
+    o.nnf_search(0, 0)
+    _, oc, od, on = o.get_state(0)
+    assert np.array_equal(oc, gc), f"{name}: {np.count_nonzero(oc != gc)} matches differ"
+    assert np.array_equal(od, gd), f"{name}: {np.count_nonzero(od != gd)} distances differ"
+    assert np.array_equal(on, gn), f"{name}: voxel counts differ"
+    del gc, gd, gn, oc, od, on
+    ref, ref_s = o.reconstruct(0, vio.WEIGHTED)
     out, _ = g.reconstruct(0, vi.WEIGHTED)
     out = host(out)
-    assert ref.shape == out.shape == (2040700, 5)
+    nH = int(mask.sum())
+    assert ref.shape == out.shape == (nH, 5)
     err = np.abs(ref.astype(np.float64) - out.astype(np.float64)).max()
-    assert err <= TOL, f"max |out_f difference| = {err}"
+    assert err <= TOL, f"{name}: max |out_f difference| = {err}"
+    hole_idx = np.flatnonzero(mask.ravel())
+    a = o.get_state(0)[0].reshape(-1, 5)[hole_idx].astype(np.int16)
+    b = host(g.get_state(0)[0]).reshape(-1, 5)[hole_idx].astype(np.int16)
+    d = np.abs(a - b)
+    assert d.max() <= 1
+    if d.any():  # uint8 flips only where the oracle's value is at a .5 boundary
+        v = ref.astype(np.float64) * 255.0
+        assert (np.abs(v - np.floor(v) - 0.5)[d > 0] <= TOL * 255.0 + 1e-3).all()
+    print(f"[case] {name}: max |out_f difference| {err:.2e}, {int((d > 0).sum())} uint8 flips",
+          flush=True)
     g.close()
     o.close()
 
 
-def test_sd_inpainting_keeps_known_pixels(vi, sd):
+@pytest.mark.timeout(900)
+def test_sd_full_level_bitexact(vi):
+    check_full_level(vi, "sd", synth.sd())
+
+
+@pytest.mark.timeout(900)
+def test_hd_full_level_bitexact(vi):
+    check_full_level(vi, "hd", synth.hd())
+
+
+def test_sd_inpainting_keeps_known_pixels(vi):
     print("[case] sd 854x480x100 full inpainting", flush=True)
+    sd = synth.sd()
     video, mask = sd.occluded_input(), sd.mask
-    g = vi.Clip(dev(video), dev(mask), **PARAMS)
+    g = vi.Clip(dev(video), dev(mask), **PARAMS["sd"])
     out = host(g.inpaint())
     g.close()
     known = mask == 0

@@ -263,3 +263,39 @@ def test_errors(vi):
     with pytest.raises(vi.ViError) as e:
         vi.Clip(dev(clip.occluded_input()), dev(m), levels=1)
     assert e.value.status == -5
+
+
+@pytest.mark.parametrize("name", ["tiny", "small2", "small3", "edge"])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_onion_layers_teacher_forced(vi, name, mode):
+    # the peel one layer at a time, each layer started from the oracle's
+    # state: the layer (erosion), the masked search of its targets and the
+    # reconstruction from contributors outside H' (Eqs. (3.10)-(3.11))
+    clip, L = CLIPS[name]()
+    o, g = make_pair(vi, clip, levels=L, seed=4, recon_mode=mode)
+    lv = L - 1
+    Hp = o.sets(lv)[0].copy()
+    gHp = dev(Hp)
+    layer = 0
+    while Hp.any():
+        if layer > 0:
+            r, c, d, n = o.get_state(lv)
+            g.set_state(lv, rgbt=r, cand=c, dist=d, nvox=n)
+        E, bd, _, oo = o.onion_layer(Hp, layer)
+        go = host(g.onion_layer(gHp, layer))
+        assert np.array_equal(E, host(gHp)), layer
+        ro, co, do, no = o.get_state(lv)
+        rg, cg, dg, ng = (host(t) for t in g.get_state(lv))
+        assert np.array_equal(co, cg), f"cand layer {layer}"
+        assert np.array_equal(do, dg), f"dist layer {layer}"
+        assert np.array_equal(no, ng), f"nvox layer {layer}"
+        px = np.flatnonzero(bd.ravel())
+        assert len(go) == len(px) == len(oo)
+        if mode == 0:
+            assert_recon_close(oo, go, ro, rg, px)
+        else:
+            assert np.array_equal(ro, rg), layer
+            assert np.abs(oo - go).max(initial=0) <= 1e-6
+        Hp = E
+        layer += 1
+    assert layer >= 2

@@ -54,3 +54,26 @@ def test_server_budget_queues_on_gpu():
     eng.close()
     assert srv.max_running == 1
     assert all(np.array_equal(o, outs[0]) for o in outs)
+
+
+def test_served_mean_results_equal_oracle():
+    # plain-mean reconstructions are exact, so every served result equals
+    # the oracle's inpainting of the same request bit for bit (Alg. 4)
+    from oracle import vio
+    print("[case] served MEAN results vs oracle", flush=True)
+    specs = [(synth.small(141 + i, 40 + 11 * i, 34 + 6 * i, 8 + i, levels=2 + i % 2, frac=0.05),
+              dict(levels=2 + i % 2, seed=400 + i, recon_mode=1)) for i in range(5)]
+    eng = GpuEngine(tune=(128, 2))
+    srv = Server(eng, hbm_budget=4 << 30, max_slots=3)
+    srv.start()
+    futs = []
+    for i, (c, kw) in enumerate(specs):
+        futs.append(srv.submit(Request(c.occluded_input(), c.mask, kw,
+                                       hole_fraction=float(c.mask.mean()))))
+        time.sleep(0.005 * (i % 2))
+    outs = [f.result(timeout=120) for f in futs]
+    srv.stop()
+    eng.close()
+    for i, (o, (c, kw)) in enumerate(zip(outs, specs)):
+        ref = vio.Oracle(c.occluded_input(), c.mask, **kw).inpaint()
+        assert np.array_equal(o, ref), i
