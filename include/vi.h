@@ -146,6 +146,20 @@ vi_status vi_onion_init(vi_ctx* ctx, int32_t* layers_run);
 vi_status vi_onion_layer(vi_ctx* ctx, uint8_t* Hp, int32_t layer, float* out_f,
                          int64_t* n_layer);
 
+/* vi_onion_layer for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same layer, the same kernels and results, but its work buffers live in a
+ * fixed 16 MiB device array of the library (one per GPU, held until the
+ * process ends) instead of memory allocated on the first call.  It calls no
+ * allocator.  The coarsest level may hold at most 1 198 336 voxels;
+ * larger levels return VI_E_BUDGET.  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (several host threads, or several
+ * streams) race and must be serialised by the caller.  Timing records
+ * (vi_profile) are not taken.  Arguments and other errors as
+ * vi_onion_layer. */
+vi_status vi_onion_layer_noalloc(vi_ctx* ctx, uint8_t* Hp, int32_t layer, float* out_f,
+                                 int64_t* n_layer);
+
 /* Level transition level+1 -> level (Sec. 3.6): nearest-neighbour upsampling
  * of the shift map and reconstruction of H^level with recon_mode. */
 vi_status vi_transition(vi_ctx* ctx, int32_t level);

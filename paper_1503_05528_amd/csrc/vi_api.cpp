@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -201,15 +202,15 @@ vi_status sync(vi_ctx* c) {
 }
 
 // stable compaction of flags into a fresh exact-size list
-vi_status compact_to(vi_ctx* c, const uint8_t* flags, int32_t n, int32_t* scratch,
+vi_status compact_to(vi_ctx* c, const uint8_t* flags, int32_t n, int32_t* tmp_list,
                      int32_t** out, int32_t* count) {
-  VI_HIP(vi::compact(c->st, flags, n, scratch, c->d_count, c->ctemp, c->ctemp_bytes));
+  VI_HIP(vi::compact(c->st, flags, n, tmp_list, c->d_count, c->ctemp, c->ctemp_bytes));
   int32_t h = 0;
   VI_HIP(hipMemcpyAsync(&h, c->d_count, sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
   VI_TRY(sync(c));
   VI_TRY(dalloc(c, out, (size_t)h));
   if (h > 0)
-    VI_HIP(hipMemcpyAsync(*out, scratch, sizeof(int32_t) * (size_t)h, hipMemcpyDeviceToDevice,
+    VI_HIP(hipMemcpyAsync(*out, tmp_list, sizeof(int32_t) * (size_t)h, hipMemcpyDeviceToDevice,
                           c->st));
   *count = h;
   return VI_OK;
@@ -392,29 +393,41 @@ vi_status onion_empty_maps(vi_ctx* c) {
   return launched("onion set-up");
 }
 
-// One layer of Alg. 3 at the coarsest level: E = erosion of H' (Hp), the
+// work buffers of one onion layer: H' and its erosion (both with
+// kMarkPad bytes before and after: the masked distance reads H' in 8-byte
+// rows), the layer and target flags, two dilation temporaries, and the
+// compact layer and target lists
+struct OnionBufs {
+  uint8_t *Hp, *E, *bd, *S, *t1, *t2;
+  int32_t *tl, *pl;
+};
+
+OnionBufs ctx_onion_bufs(vi_ctx* c) {
+  return OnionBufs{c->o_Hp, c->o_E, c->o_bd, c->o_S, c->o_t1, c->o_t2, c->o_tl, c->o_pl};
+}
+
+// One layer of Alg. 3 at the coarsest level: E = erosion of H' (B.Hp), the
 // layer bd = H' \ E and its targets S = dilate(bd) \ H'; search of S with
 // the distance over voxels outside H', reconstruction of bd from the
 // contributors outside H'.  *nb receives |bd| (0: H' is empty, nothing
 // searched).  Syncs.
-vi_status onion_step(vi_ctx* c, const uint8_t* Hp, uint8_t* E, int32_t layer, float* out_f,
-                     int32_t* nb) {
+vi_status onion_step(vi_ctx* c, const OnionBufs& B, int32_t layer, float* out_f, int32_t* nb) {
   const int32_t level = c->L - 1;
   const vi::DevLevel& d = c->lv[level].d;
   const int r = prof_begin(c, VI_K_OTHER);
-  vi::launch_erode3(c->st, Hp, E, c->o_bd, d.W, d.H, d.T);
-  vi::launch_dilate5(c->st, c->o_bd, c->o_S, c->o_t1, c->o_t2, d.W, d.H, d.T, Hp);
+  vi::launch_erode3(c->st, B.Hp, B.E, B.bd, d.W, d.H, d.T);
+  vi::launch_dilate5(c->st, B.bd, B.S, B.t1, B.t2, d.W, d.H, d.T, B.Hp);
   prof_end(c, r, VI_K_OTHER, level, d.V);
   VI_TRY(launched("onion layer"));
-  VI_HIP(vi::compact(c->st, c->o_bd, d.V, c->o_pl, c->d_count, c->ctemp, c->ctemp_bytes));
-  VI_HIP(vi::compact(c->st, c->o_S, d.V, c->o_tl, c->d_count + 1, c->ctemp, c->ctemp_bytes));
+  VI_HIP(vi::compact(c->st, B.bd, d.V, B.pl, c->d_count, c->ctemp, c->ctemp_bytes));
+  VI_HIP(vi::compact(c->st, B.S, d.V, B.tl, c->d_count + 1, c->ctemp, c->ctemp_bytes));
   int32_t cnt[2] = {0, 0};
   VI_HIP(hipMemcpyAsync(cnt, c->d_count, sizeof(cnt), hipMemcpyDeviceToHost, c->st));
   VI_TRY(sync(c));
   *nb = cnt[0];
   if (cnt[0] == 0) return VI_OK;
-  VI_TRY(search(c, level, c->o_tl, cnt[1], c->o_S, Hp, (uint64_t(1) << 32) + (uint64_t)layer));
-  return recon(c, level, c->o_pl, cnt[0], Hp, c->prm.recon_mode, out_f, nullptr);
+  VI_TRY(search(c, level, B.tl, cnt[1], B.S, B.Hp, (uint64_t(1) << 32) + (uint64_t)layer));
+  return recon(c, level, B.pl, cnt[0], B.Hp, c->prm.recon_mode, out_f, nullptr);
 }
 
 // the start of a peel: scratch, empty shift maps, H' = the coarsest hole
@@ -430,8 +443,7 @@ vi_status onion(vi_ctx* c, int32_t* layers_run) {
   const int32_t level = c->L - 1;
   Level& lv = c->lv[level];
   VI_TRY(onion_prepare(c));
-  uint8_t* Hp = c->o_Hp;
-  uint8_t* E = c->o_E;
+  OnionBufs B = ctx_onion_bufs(c);
   int32_t layer = 0;
   struct Kind {
     vi_ctx* c;
@@ -440,11 +452,9 @@ vi_status onion(vi_ctx* c, int32_t* layers_run) {
   c->kind_override = VI_K_ONION;
   for (;;) {
     int32_t nb = 0;
-    VI_TRY(onion_step(c, Hp, E, layer, nullptr, &nb));
+    VI_TRY(onion_step(c, B, layer, nullptr, &nb));
     if (nb == 0) break;  // no layer left: H' is empty
-    uint8_t* t = Hp;
-    Hp = E;
-    E = t;
+    std::swap(B.Hp, B.E);
     ++layer;
   }
   lv.complete = false;  // the innermost layer's targets may be unmatched
@@ -463,6 +473,85 @@ vi_status transition(vi_ctx* c, int32_t level) {
   F.complete = true;
   F.recon_ok = false;  // the upsampling sets no reconstruction marks
   return recon(c, level, F.hlist, F.nH, nullptr, c->prm.recon_mode, nullptr, nullptr);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Fixed scratch of vi_onion_layer_noalloc: one array per GPU, resolved once
+// per device with hipGetSymbolAddress; host code uses only the resolved
+// device address, never the array's name.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kNoAllocBytes = size_t(16) << 20;
+constexpr int kNoAllocDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kNoAllocDevices] = {};
+
+// bytes of one 256-aligned segment
+size_t seg(size_t b) { return (b + 255) & ~size_t(255); }
+
+// scratch bytes one onion layer needs for a level of V voxels
+size_t noalloc_bytes(size_t V) {
+  return 2 * seg(V + 2 * vi::kMarkPad) + 4 * seg(V) + 2 * seg(4 * V);
+}
+
+// the largest V with noalloc_bytes(V) <= kNoAllocBytes (1 198 336)
+int64_t noalloc_max_voxels() {
+  int64_t lo = 0, hi = (int64_t)kNoAllocBytes;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (noalloc_bytes((size_t)mid) <= kNoAllocBytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+OnionBufs noalloc_bufs(unsigned char* base, size_t V) {
+  OnionBufs B{};
+  size_t o = 0;
+  B.Hp = base + o + vi::kMarkPad;
+  o += seg(V + 2 * vi::kMarkPad);
+  B.E = base + o + vi::kMarkPad;
+  o += seg(V + 2 * vi::kMarkPad);
+  uint8_t** flags[4] = {&B.bd, &B.S, &B.t1, &B.t2};
+  for (uint8_t** f : flags) {
+    *f = base + o;
+    o += seg(V);
+  }
+  B.tl = reinterpret_cast<int32_t*>(base + o);
+  o += seg(4 * V);
+  B.pl = reinterpret_cast<int32_t*>(base + o);
+  return B;
+}
+
+// the device address of this device's scratch array (set up once per device,
+// with that device current)
+vi_status noalloc_scratch(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kNoAllocDevices) return fail(VI_E_INVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    VI_HIP(hipGetDevice(&cur));
+    if (cur != dev) VI_HIP(hipSetDevice(dev));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+      return fail(VI_E_HIP, std::string("hipGetSymbolAddress(scratch) failed: ") +
+                                hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return VI_OK;
 }
 
 }  // namespace
@@ -583,9 +672,9 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
   uint32_t* gpk = nullptr;
   uint2* hsum = nullptr;
   uint8_t *t1 = nullptr, *t2 = nullptr;
-  int32_t* scratch = nullptr;
+  int32_t* tmp_list = nullptr;
   if ((st = dalloc(c, &gpk, V0)) || (st = dalloc(c, &hsum, V0)) || (st = dalloc(c, &t1, V0)) ||
-      (st = dalloc(c, &t2, V0)) || (st = dalloc(c, &scratch, V0)))
+      (st = dalloc(c, &t2, V0)) || (st = dalloc(c, &tmp_list, V0)))
     return bail(st);
   // pyramids (Alg. 4) and texture features (Sec. 3.3)
   vi::launch_init_level0(c->st, video_rgb, mask, L0);
@@ -603,9 +692,9 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
     vi::launch_fill_nnf(c->st, d.nnf0, d.nvox, d.V);
     vi::launch_fill_nnf(c->st, d.nnf1, nullptr, d.V);
     if ((st = launched("sets"))) return bail(st);
-    if ((st = compact_to(c, d.dsrc, d.V, scratch, &d.dlist, &d.nD))) return bail(st);
-    if ((st = compact_to(c, d.htil, d.V, scratch, &lv.tlist, &lv.nS))) return bail(st);
-    if ((st = compact_to(c, d.hole, d.V, scratch, &lv.hlist, &lv.nH))) return bail(st);
+    if ((st = compact_to(c, d.dsrc, d.V, tmp_list, &d.dlist, &d.nD))) return bail(st);
+    if ((st = compact_to(c, d.htil, d.V, tmp_list, &lv.tlist, &lv.nS))) return bail(st);
+    if ((st = compact_to(c, d.hole, d.V, tmp_list, &lv.hlist, &lv.nH))) return bail(st);
     if (d.nD == 0) return bail(fail(VI_E_EMPTY_SOURCE, "level " + std::to_string(l) +
                                                            " has no hole-free patch"));
   }
@@ -614,7 +703,7 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
   dfree(c, hsum);
   dfree(c, t1);
   dfree(c, t2);
-  dfree(c, scratch);
+  dfree(c, tmp_list);
   *out = c;
   return VI_OK;
 }
@@ -712,8 +801,44 @@ vi_status vi_onion_layer(vi_ctx* c, uint8_t* Hp, int32_t layer, float* out_f,
   } kind_guard{c};
   c->kind_override = VI_K_ONION;
   int32_t nb = 0;
-  VI_TRY(onion_step(c, c->o_Hp, c->o_E, layer, out_f, &nb));
+  VI_TRY(onion_step(c, ctx_onion_bufs(c), layer, out_f, &nb));
   VI_HIP(hipMemcpyAsync(Hp, c->o_E, V, hipMemcpyDeviceToDevice, c->st));
+  lv.complete = false;  // the inner layers' targets may be unmatched
+  if (n_layer) *n_layer = nb;
+  return sync(c);
+}
+
+vi_status vi_onion_layer_noalloc(vi_ctx* c, uint8_t* Hp, int32_t layer, float* out_f,
+                                 int64_t* n_layer) {
+  if (!c || !Hp) return fail(VI_E_INVAL, "null argument");
+  if (layer < 0) return fail(VI_E_INVAL, "layer must be >= 0");
+  if (c->batch) return fail(VI_E_STATE, "the clip is in a batch");
+  Level& lv = c->lv[c->L - 1];
+  const size_t V = (size_t)lv.d.V;
+  if (noalloc_bytes(V) > kNoAllocBytes)
+    return fail(VI_E_BUDGET, "the coarsest level has more voxels than the fixed scratch of "
+                             "vi_onion_layer_noalloc holds (" +
+                                 std::to_string(noalloc_max_voxels()) + ")");
+  unsigned char* base = nullptr;
+  VI_TRY(noalloc_scratch(c->dev, &base));
+  const OnionBufs B = noalloc_bufs(base, V);
+  // no timing events either: they may be created on first use
+  struct Prof {
+    vi_ctx* c;
+    uint32_t mask;
+    ~Prof() {
+      c->prof_mask = mask;
+      c->kind_override = -1;
+    }
+  } prof_guard{c, c->prof_mask};
+  c->prof_mask = 0;
+  c->kind_override = VI_K_ONION;
+  if (layer == 0) VI_TRY(onion_empty_maps(c));
+  lv.recon_ok = false;
+  VI_HIP(hipMemcpyAsync(B.Hp, Hp, V, hipMemcpyDeviceToDevice, c->st));
+  int32_t nb = 0;
+  VI_TRY(onion_step(c, B, layer, out_f, &nb));
+  VI_HIP(hipMemcpyAsync(Hp, B.E, V, hipMemcpyDeviceToDevice, c->st));
   lv.complete = false;  // the inner layers' targets may be unmatched
   if (n_layer) *n_layer = nb;
   return sync(c);

@@ -56,6 +56,7 @@ SIGNATURES = {
     "vi_inpaint_level": (_i32, [_vp, _i32, C.POINTER(_i32)]),
     "vi_onion_init": (_i32, [_vp, C.POINTER(_i32)]),
     "vi_onion_layer": (_i32, [_vp, _vp, _i32, _vp, C.POINTER(C.c_int64)]),
+    "vi_onion_layer_noalloc": (_i32, [_vp, _vp, _i32, _vp, C.POINTER(C.c_int64)]),
     "vi_transition": (_i32, [_vp, _i32]),
     "vi_inpaint": (_i32, [_vp, _vp]),
     "vi_get_state": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp]),
@@ -279,15 +280,19 @@ class Clip:
         _check("vi_onion_init", lib().vi_onion_init(self.h, C.byref(k)))
         return int(k.value)
 
-    def onion_layer(self, Hp, layer):
+    def onion_layer(self, Hp, layer, out=None, noalloc=False):
         """One onion-peel layer: Hp (device uint8 [T][H][W] of the coarsest
         level) is replaced by its erosion; returns the layer's reconstructed
-        values [|layer|][5] in [0,1]."""
-        nb = int(torch.count_nonzero(Hp))
-        out = self._new((max(nb, 1), 5), torch.float32)
+        values [|layer|][5] in [0,1].  out: a float32 device buffer of at
+        least |layer| rows to write them to (else one is allocated);
+        noalloc: the variant whose work buffers are the library's fixed
+        scratch (vi_onion_layer_noalloc)."""
+        if out is None:
+            nb = int(torch.count_nonzero(Hp))
+            out = self._new((max(nb, 1), 5), torch.float32)
         n = C.c_int64(0)
-        _check("vi_onion_layer", lib().vi_onion_layer(self.h, _ptr(Hp), layer, _ptr(out),
-                                                      C.byref(n)))
+        name = "vi_onion_layer_noalloc" if noalloc else "vi_onion_layer"
+        _check(name, getattr(lib(), name)(self.h, _ptr(Hp), layer, _ptr(out), C.byref(n)))
         return out[:int(n.value)]
 
     def transition(self, level):
