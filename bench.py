@@ -1,11 +1,13 @@
 """Benchmark of the inpainting hot path on one MI355X.
 
-A step is one complete inpainting of the SD clip (854x480 px x 100 frames,
-4-level pyramid, 5x5x5 patches, 20 EM iterations per level): context
-creation (pyramids, texture features, sets), onion-peel initialisation, the
-EM loop of every level (ANN search + weighted reconstruction), level
-transitions and the final best-patch reconstruction, from the input video
-resident in HBM to the output video in HBM.
+A step is one complete inpainting of one clip: context creation (pyramids,
+texture features, sets), onion-peel initialisation, the EM loop of every
+level (ANN search + weighted reconstruction, 20 iterations per level),
+level transitions and the final best-patch reconstruction, from the input
+video resident in HBM to the output video in HBM.  The headline workload is
+the HD clip (1920x1080 px x 60 frames, 5-level pyramid, the largest
+single-GPU configuration); the SD clip (854x480 px x 100 frames, 4 levels)
+is measured in the same run and reported under "sd".
 
 Prints one JSON line.  `value` is nominal NNF patch-distance evaluations per
 second over the timed steps (the nominal count of a search is |H~| x (1 + sum
@@ -13,9 +15,11 @@ over iterations of 6 n_jf + [radius >= 1]) and does not depend on how many
 candidates an implementation skips).  The roofline object covers the
 propagation-pass kernel, timed with HIP events on the context's stream over
 the timed steps (one event pair around the back-to-back passes of each
-search; the average launch duration is their time over their count); the
-CPU baseline is the oracle's search at level 1 of the
-same clip on the host cores.
+search; the average launch duration is their time over their count); its
+binding roof is the one the hardware counters of the same kernel show
+nearer to saturation (HBM traffic against the box's copy rate, or VALU
+issue).  The CPU baseline is the oracle's search over a sample of the
+finest level's targets of the same clip, on all host cores and on one.
 """
 import argparse
 import json
@@ -28,20 +32,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: int32 VALU lane operations per second
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 BYTES_PER_EVAL = 625  # 125 voxels x 5 uint8 channels of the candidate patch
-BYTES_PER_TARGET_PASS = 32  # shift-map state: six 4-byte neighbour reads, one 8-byte write
+# per target and pass: its own patch through the workgroup's tile (5 B) and
+# the shift-map state (six 4-byte neighbour reads, one 8-byte write)
+BYTES_PER_TARGET_PASS = 37
+OPS_PER_EVAL = 1250  # 625 subtractions + 625 multiply-adds (5 channels x 125 voxels)
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="sd", choices=["sd", "hd", "tiny"])
+    ap.add_argument("--config", default="hd", choices=["sd", "hd", "tiny"])
+    ap.add_argument("--no-sd", action="store_true",
+                    help="skip the SD clip measured beside the headline workload")
+    ap.add_argument("--sd-steps", type=int, default=3)
     ap.add_argument("--em-iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-level", type=int, default=1)
-    ap.add_argument("--cpu-searches", type=int, default=3)
+    ap.add_argument("--cpu-frames", type=int, default=60,
+                    help="frames of the crop whose finest level the all-core oracle sample "
+                         "searches")
+    ap.add_argument("--cpu-frames-1core", type=int, default=10,
+                    help="frames of the crop the one-core oracle sample searches")
+    ap.add_argument("--cpu-sample-run", nargs=2, metavar=("CONFIG", "FRAMES"),
+                    help=argparse.SUPPRESS)
     ap.add_argument("--oracle-timing", action="store_true",
                     help="time the oracle on one host core and on all of them and exit")
     ap.add_argument("--oracle-timing-run", action="store_true", help=argparse.SUPPRESS)
@@ -54,15 +71,18 @@ def parse():
     ap.add_argument("--served-rate", type=float, default=4.0)
     ap.add_argument("--summarize-counters", metavar="DIR",
                     help="summarise a rocprofv3 --output-format csv directory and exit")
-    ap.add_argument("--assemble-counters", nargs=4,
-                    metavar=("PASS_FETCH", "PASS_WRITE", "COPY_FETCH", "COPY_WRITE"),
+    ap.add_argument("--assemble-counters", nargs=5,
+                    metavar=("PASS_FETCH", "PASS_WRITE", "PASS_SQ", "COPY_FETCH", "COPY_WRITE"),
                     help="write the search kernel's HBM traffic record from four "
                          "--summarize-counters outputs (JSON files) and exit")
     return ap.parse_args()
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1503_05528_amd", "csrc", "vi_kernels.hip")
-COUNTERS_JSON = os.path.join(ROOT, "profiles", "k_pass_sd_hbm_counters.json")
+
+
+def counters_json(workload):
+    return os.path.join(ROOT, "profiles", f"k_pass_{workload}_counters.json")
 
 
 def log(msg):
@@ -101,49 +121,78 @@ def summarize_counters(d):
 PASS_KERNEL = "vi::k_pass<false>"
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_BYTES = 1 << 30
+SQ_COUNTERS = "SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VMEM_RD SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT GRBM_GUI_ACTIVE"
 
 
-def assemble_counters(pass_fetch, pass_write, copy_fetch, copy_write, workload):
-    """HBM bytes per launch of the search kernel: FETCH_SIZE and WRITE_SIZE
-    (KiB per dispatch, averaged over every dispatch of the kernel at every
-    grid size) scaled by what the same counters read for a plain 1 GiB
-    device copy, which reads and writes exactly COPY_BYTES."""
-    def load(path, kernel, counter):
+def assemble_counters(pass_fetch, pass_write, pass_sq, copy_fetch, copy_write, workload):
+    """The search kernel's counter record: HBM bytes per launch from
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch, averaged over every
+    dispatch of the kernel at every grid size) scaled by what the same
+    counters read for a plain 1 GiB device copy, which reads and writes
+    exactly COPY_BYTES; VALU issue from SQ_INSTS_VALU (wave instructions; a
+    CU issues at most one per cycle across its four SIMDs) over the
+    dispatch's cycles at 2.4 GHz on 256 CUs."""
+    def load(path, kernel):
         rows = [r for r in json.load(open(path)) if r["kernel"] == kernel]
         n = sum(r["dispatches"] for r in rows)
         if n == 0:
             raise SystemExit(f"{path}: no dispatch of {kernel}")
-        v = sum(r["counters"][counter] * r["dispatches"] for r in rows) / n
-        us = sum(r["mean_us"] * r["dispatches"] for r in rows) / n
-        return v, us, n
-    fk, us, n = load(pass_fetch, PASS_KERNEL, "FETCH_SIZE")
-    wk, _, _ = load(pass_write, PASS_KERNEL, "WRITE_SIZE")
-    cf, cus, _ = load(copy_fetch, COPY_KERNEL, "FETCH_SIZE")
-    cw, _, _ = load(copy_write, COPY_KERNEL, "WRITE_SIZE")
+        return rows, n
+
+    def mean(rows, n, counter):
+        return sum(r["counters"][counter] * r["dispatches"] for r in rows) / n
+
+    def mean_us(rows, n):
+        return sum(r["mean_us"] * r["dispatches"] for r in rows) / n
+    rf, nf = load(pass_fetch, PASS_KERNEL)
+    rw, nw = load(pass_write, PASS_KERNEL)
+    rs, ns = load(pass_sq, PASS_KERNEL)
+    cf_rows, cfn = load(copy_fetch, COPY_KERNEL)
+    cw_rows, cwn = load(copy_write, COPY_KERNEL)
+    fk, wk = mean(rf, nf, "FETCH_SIZE"), mean(rw, nw, "WRITE_SIZE")
+    cf, cw = mean(cf_rows, cfn, "FETCH_SIZE"), mean(cw_rows, cwn, "WRITE_SIZE")
     fscale = COPY_BYTES / 1024.0 / cf
     wscale = COPY_BYTES / 1024.0 / cw
+    us = mean_us(rf, nf)
+    sq = {c: mean(rs, ns, c) for c in SQ_COUNTERS.split()}
+    sq_us = mean_us(rs, ns)
+    per_level = []
+    for r in sorted(rf, key=lambda r: -r["grid"]):
+        w = next((x for x in rw if x["grid"] == r["grid"]), None)
+        q = next((x for x in rs if x["grid"] == r["grid"]), None)
+        hb = 1024.0 * (r["counters"]["FETCH_SIZE"] * fscale
+                       + (w["counters"]["WRITE_SIZE"] * wscale if w else 0.0))
+        per_level.append({
+            "grid": r["grid"], "dispatches": r["dispatches"], "mean_us": r["mean_us"],
+            "hbm_bytes_per_launch": hb, "hbm_gbs": hb / (r["mean_us"] * 1e-6) / 1e9,
+            "valu_busy": (q["counters"]["SQ_INSTS_VALU"] / (256 * q["mean_us"] * 2400.0)
+                          if q else None)})
     rec = {
         "kernel": PASS_KERNEL, "workload": workload, "source_sha256": kernel_source_hash(),
         "fetch_kib_per_launch": fk, "write_kib_per_launch": wk,
         "fetch_scale": fscale, "write_scale": wscale,
         "hbm_bytes_per_launch": 1024.0 * (fk * fscale + wk * wscale),
-        "mean_launch_us": us, "dispatches": n,
+        "mean_launch_us": us, "dispatches": nf,
+        "sq_per_launch": sq, "sq_mean_launch_us": sq_us,
+        "valu_busy": sq["SQ_INSTS_VALU"] / (256 * sq_us * 2400.0),
+        "per_grid": per_level,
         "copy_calibration": {"bytes": COPY_BYTES, "FETCH_SIZE_kib": cf, "WRITE_SIZE_kib": cw,
-                             "mean_us": cus},
+                             "mean_us": mean_us(cf_rows, cfn)},
         "commands": [
-            "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --kernel-include-regex k_pass "
-            "--output-format csv -d /tmp/p_FETCH_SIZE -o run -- python $REPO/bench.py "
-            "--no-cpu-baseline --no-batched --no-served --steps 1 --warmup 0",
-            "(the same with WRITE_SIZE)",
+            f"cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --kernel-include-regex k_pass "
+            f"--output-format csv -d /tmp/p_FETCH_SIZE -o run -- python $REPO/bench.py "
+            f"--config {workload} --no-sd --no-cpu-baseline --no-batched --no-served "
+            f"--steps 1 --warmup 0",
+            "(the same with --pmc WRITE_SIZE, and with --pmc " + SQ_COUNTERS + ")",
             "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv "
             "-d /tmp/c_FETCH_SIZE -o run -- python $REPO/bench.py --copy-calibration "
             "(and the same with WRITE_SIZE)",
-            "python $REPO/bench.py --summarize-counters <dir> > <json>   (each of the four)",
-            "python $REPO/bench.py --assemble-counters <pass FETCH> <pass WRITE> "
-            "<copy FETCH> <copy WRITE>",
+            "python $REPO/bench.py --summarize-counters <dir> > <json>   (each of the five)",
+            "python $REPO/bench.py --config " + workload + " --assemble-counters <pass FETCH> "
+            "<pass WRITE> <pass SQ> <copy FETCH> <copy WRITE>",
         ],
     }
-    with open(COUNTERS_JSON, "w") as f:
+    with open(counters_json(workload), "w") as f:
         json.dump(rec, f, indent=1)
         f.write("\n")
     return rec
@@ -321,16 +370,28 @@ def make_clip(name):
     return synth.tiny(), 1
 
 
-def cpu_baseline(clip, levels, em_iters, level, searches):
-    """The oracle, as it stands, on a bounded sample of the workload: a few
-    ANN searches (successive EM indices, each from the previous shift map) at
-    a coarser level of the same clip, on all host threads."""
+# crops (x0, x1, y0, y1) around an occlusion of each clip, for the oracle's
+# timing samples
+CPU_CROPS = {"hd": (240, 600, 160, 340), "sd": (220, 640, 170, 310), "tiny": (0, 32, 0, 32)}
+
+
+def cpu_sample_run(config, frames):
+    """One process's oracle timing (its OpenMP thread count comes from the
+    environment): a complete ANN search of the finest level of a crop of the
+    clip (its frames [0, frames) and the CPU_CROPS window, same pyramid
+    depth), from the unset shift map (random initialisation, then every
+    iteration; the oracle evaluates every candidate in full, so its cost
+    does not depend on the state)."""
+    import numpy as np
     from oracle import vio
-    o = vio.Oracle(clip.occluded_input(), clip.mask, levels=levels, em_tol=-1.0,
-                   em_max_iters=em_iters, seed=1)
-    (W, H, T), (nH, nS, nD) = o.info(level)
-    per = 1
+    clip, levels = make_clip(config)
+    x0, x1, y0, y1 = CPU_CROPS[config]
+    video = np.ascontiguousarray(clip.occluded_input()[:frames, y0:y1, x0:x1])
+    mask = np.ascontiguousarray(clip.mask[:frames, y0:y1, x0:x1])
+    o = vio.Oracle(video, mask, levels=levels, em_tol=-1.0, seed=1)
+    (W, H, T), (_, nS, _) = o.info(0)
     p = o.params
+    per = 1
     rmax = max(W, H, T)
     for k in range(1, p.pm_iters + 1):
         r = float(rmax)
@@ -338,14 +399,36 @@ def cpu_baseline(clip, levels, em_iters, level, searches):
             r *= p.rho
         per += 6 * p.n_jf + (1 if int(r // 1) >= 1 else 0)
     t0 = time.perf_counter()
-    for k in range(searches):
-        o.nnf_search(level, k)
+    o.nnf_search(0, 0)
     dt = time.perf_counter() - t0
-    evals = per * nS * searches
-    return {"value": evals / dt, "unit": "evals/s", "cores": vio.num_threads(),
-            "kind": "oracle",
-            "sample": f"{searches} vio_nnf_search calls at pyramid level {level} of the same "
-                      f"clip ({W}x{H}x{T}, {nS} targets, {evals} nominal evals, {dt:.1f} s)"}
+    print(json.dumps({"threads": vio.num_threads(), "targets": nS, "evals": per * nS,
+                      "seconds": dt, "dims": [W, H, T], "crop": [x0, x1, y0, y1]}), flush=True)
+
+
+def cpu_baseline(config, frames_all, frames_one):
+    """The oracle, as it stands, on a bounded sample of the workload: the
+    complete finest-level search of a crop of the clip around an occlusion,
+    on all host threads, and of a shorter crop on one thread."""
+    import subprocess
+    out = {}
+    for key, n, fr in (("all", os.cpu_count() or 1, frames_all), ("one", 1, frames_one)):
+        env = dict(os.environ, OMP_NUM_THREADS=str(n))
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-sample-run",
+                            config, str(fr)], env=env, capture_output=True, text=True,
+                           check=True)
+        out[key] = json.loads(r.stdout.strip().splitlines()[-1])
+    a, b = out["all"], out["one"]
+    x0, x1, y0, y1 = a["crop"]
+
+    def desc(r):
+        W, H, T = r["dims"]
+        return (f"vio_nnf_search of the finest level of the {config} clip cropped to "
+                f"x {x0}-{x1 - 1}, y {y0}-{y1 - 1}, frames 0-{T - 1} ({W}x{H}x{T}, "
+                f"{r['targets']} targets): {r['evals']} nominal evals in {r['seconds']:.1f} s")
+    return {"value": a["evals"] / a["seconds"], "unit": "evals/s", "cores": a["threads"],
+            "kind": "oracle", "sample": desc(a),
+            "one_core": {"value": b["evals"] / b["seconds"], "unit": "evals/s", "cores": 1,
+                         "sample": desc(b)}}
 
 
 def oracle_timing_run():
@@ -401,6 +484,153 @@ def oracle_timing():
     print(json.dumps({"oracle_timing": res}), flush=True)
 
 
+def percentile(xs, q):
+    """Nearest-rank percentile (q in (0, 1]) of a list."""
+    ys = sorted(xs)
+    k = max(1, int(-(-q * len(ys) // 1)))  # ceil(q n)
+    return ys[min(k, len(ys)) - 1]
+
+
+def roofline_of(workload, pass_evals, pass_units, pass_ms, pass_launches, nominal,
+                targets_per_search):
+    """Roofline record of the propagation-pass kernel from a run's device
+    counters and event times, and the counter record of the same kernel
+    (profiles/k_pass_<workload>_counters.json) while its source matches."""
+    avg_ms = pass_ms / pass_launches
+    evals_per_launch = pass_evals / pass_launches
+    targets_per_launch = pass_units / pass_launches
+    bytes_per_launch = (BYTES_PER_EVAL * evals_per_launch
+                        + BYTES_PER_TARGET_PASS * targets_per_launch)
+    gbs = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    tops = OPS_PER_EVAL * evals_per_launch / (avg_ms * 1e-3) / 1e12
+    # nominal evaluations of the passes: all of a step's minus one per target
+    # per search (step 0); the onion peel's share (< 1 %) is included
+    nominal_pass_per_launch = (nominal - targets_per_search) / pass_launches
+    cnt = None
+    path = counters_json(workload)
+    if os.path.exists(path):
+        cj = json.load(open(path))
+        cc = cj.get("copy_calibration") or {}
+        copy_gbs = (2.0 * cc["bytes"] / (cc["mean_us"] * 1e-6) / 1e9) if cc.get("mean_us") else None
+        if cj.get("source_sha256") == kernel_source_hash():
+            hbm_gbs = cj["hbm_bytes_per_launch"] / (cj["mean_launch_us"] * 1e-6) / 1e9
+            cnt = {"hbm_bytes_per_launch": round(cj["hbm_bytes_per_launch"]),
+                   "hbm_gbs": round(hbm_gbs, 1),
+                   "achievable_copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
+                   "hbm_frac_of_copy": None if copy_gbs is None else round(hbm_gbs / copy_gbs, 4),
+                   "hbm_frac_of_peak": round(hbm_gbs / HBM_PEAK_GBS, 4),
+                   "valu_busy": round(cj["valu_busy"], 4),
+                   "profiled_mean_launch_us": round(cj["mean_launch_us"], 2),
+                   "record": os.path.relpath(path, ROOT)}
+    # the binding roof: the one the counters show nearer to saturation
+    if cnt and cnt["hbm_frac_of_copy"] is not None and cnt["valu_busy"] > cnt["hbm_frac_of_copy"]:
+        bound, achieved, peak, unit = "alu", tops, VALU_PEAK_TOPS, "TOP/s"
+    else:
+        bound, achieved, peak, unit = "hbm", gbs, HBM_PEAK_GBS, "GB/s"
+    limiter = None
+    if cnt:
+        top = max(cnt["valu_busy"], cnt["hbm_frac_of_copy"] or 0.0)
+        limiter = ("latency: neither the VALU nor HBM traffic reaches half of its roof"
+                   if top < 0.5 else f"{bound} roof")
+    return {
+        "bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": unit,
+        "frac": round(achieved / peak, 4),
+        "traffic": None if cnt is None else cnt["hbm_bytes_per_launch"],
+        "kernel": "k_pass<false> (propagation pass with fused random search)",
+        "avg_launch_ms": round(avg_ms, 5), "launches": pass_launches,
+        "evals_per_launch": round(evals_per_launch, 1),
+        "target_passes_per_launch": round(targets_per_launch, 1),
+        "algorithmic_bytes_per_launch": round(bytes_per_launch),
+        "algorithmic_gbs": round(gbs, 1), "algorithmic_frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+        "algorithmic_int_tops": round(tops, 3),
+        "algorithmic_frac_of_valu_peak": round(tops / VALU_PEAK_TOPS, 4),
+        "nominal_evals_per_launch": round(nominal_pass_per_launch, 1),
+        "nominal_gather_gbs": round(BYTES_PER_EVAL * nominal_pass_per_launch
+                                    / (avg_ms * 1e-3) / 1e9, 1),
+        "counters": cnt, "limiter": limiter,
+    }
+
+
+def measure_plain(config, steps, warmup, em_iters):
+    """Whole inpaintings of one clip from inputs resident in HBM: timed
+    steps, per-kind kernel time of one more step, and the roofline record."""
+    import torch
+    from paper_1503_05528_amd import vi
+    clip, levels = make_clip(config)
+    W, H, T = clip.shape
+    video = torch.from_numpy(clip.occluded_input()).cuda()
+    mask = torch.from_numpy(clip.mask).cuda()
+    params = vi.default_params(levels=levels, em_tol=-1.0, em_max_iters=em_iters, seed=1)
+    torch.cuda.synchronize()
+
+    def one_step(profile=None):
+        g = vi.Clip(video, mask, params=params)
+        if profile:
+            g.profile(True, kinds=profile)
+        out = g.inpaint()
+        rec = g.profile_read() if profile else []
+        cnt = g.counters()
+        g.close()
+        return out, rec, cnt
+
+    log(f"{config}: {warmup} warm-up and {steps} timed steps")
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    lat = []
+    recs = []
+    nominal = effective = pass_evals = 0
+    t0 = time.perf_counter()
+    # inside the timed region only the search passes (the roofline's kernel)
+    # are timed with events; every event pair costs the stream a few tens of
+    # microseconds
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        out, rec, cnt = one_step(profile=("pass",))
+        lat.append(time.perf_counter() - s0)
+        recs += rec
+        nominal += cnt["nominal_evals"]
+        effective += cnt["effective_evals"]
+        pass_evals += cnt["pass_evals"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    def by_kind(rs):
+        kinds = {}
+        for kind, lvl, units, ms, nl in rs:
+            d = kinds.setdefault(kind, {"launches": 0, "units": 0, "ms": 0.0})
+            d["launches"] += nl
+            d["units"] += units
+            d["ms"] += ms
+            d["targets_per_search"] = d.get("targets_per_search", 0) + units / max(nl, 1)
+        return kinds
+    kinds = by_kind(recs)
+    # per kind and level: one more step, after the timed region, with every
+    # kind timed
+    _, all_recs, _ = one_step(profile=tuple(vi.KERNEL_KINDS.values()))
+    by_level = {}
+    for kind, lvl, units, ms, nl in all_recs:
+        key = f"{kind}@L{lvl}"
+        by_level[key] = round(by_level.get(key, 0.0) + ms, 3)
+    pas = kinds.get("pass", {"launches": 1, "units": 0, "ms": 1.0, "targets_per_search": 0})
+    roof = roofline_of(config, pass_evals, pas["units"], pas["ms"], pas["launches"], nominal,
+                       pas["targets_per_search"])
+    return {
+        "value": nominal / elapsed, "ms_per_step": 1000.0 * elapsed / steps,
+        "clips_per_s": steps / elapsed, "steps": steps, "warmup": warmup,
+        "workload": f"{config} plain run {W}x{H}x{T}, {levels}-level pyramid, 5x5x5 patches, "
+                    f"{em_iters} EM iterations per level, one clip per step",
+        "latency_p50_ms": 1000 * percentile(lat, 0.5),
+        "latency_p99_ms": 1000 * percentile(lat, 0.99),
+        "latency_samples": len(lat),
+        "effective_evals_per_s": effective / elapsed,
+        "kernel_ms_per_step": {k: round(v["ms"], 3) for k, v in by_kind(all_recs).items()},
+        "kernel_ms_per_step_by_level": by_level,
+        "roofline": roof,
+        "clip": (clip, levels),
+    }
+
+
 def main():
     a = parse()
     if a.oracle_timing_run:
@@ -408,6 +638,9 @@ def main():
         return
     if a.oracle_timing:
         oracle_timing()
+        return
+    if a.cpu_sample_run:
+        cpu_sample_run(a.cpu_sample_run[0], int(a.cpu_sample_run[1]))
         return
     if a.summarize_counters:
         print(json.dumps(summarize_counters(a.summarize_counters), indent=1))
@@ -433,129 +666,45 @@ def main():
         return
 
     vi.lib()
-    clip, levels = make_clip(a.config)
-    W, H, T = clip.shape
-    video = torch.from_numpy(clip.occluded_input()).cuda()
-    mask = torch.from_numpy(clip.mask).cuda()
-    params = vi.default_params(levels=levels, em_tol=-1.0, em_max_iters=a.em_iters, seed=1)
-    torch.cuda.synchronize()
-
-    def one_step(profile=None):
-        g = vi.Clip(video, mask, params=params)
-        if profile:
-            g.profile(True, kinds=profile)
-        out = g.inpaint()
-        rec = g.profile_read() if profile else []
-        cnt = g.counters()
-        g.close()
-        return out, rec, cnt
-
-    log(f"{a.config}: {a.warmup} warm-up and {a.steps} timed steps")
-    for _ in range(a.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    lat = []
-    recs = []
-    nominal = effective = pass_evals = 0
-    t0 = time.perf_counter()
-    # inside the timed region only the search passes (the roofline's kernel)
-    # are timed with events; every event pair costs the stream a few tens of
-    # microseconds
-    for _ in range(a.steps):
-        s0 = time.perf_counter()
-        out, rec, cnt = one_step(profile=("pass",))
-        lat.append(time.perf_counter() - s0)
-        recs += rec
-        nominal += cnt["nominal_evals"]
-        effective += cnt["effective_evals"]
-        pass_evals += cnt["pass_evals"]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = 1000.0 * elapsed / a.steps
-
-    def by_kind(rs):
-        kinds = {}
-        for kind, lvl, units, ms, nl in rs:
-            d = kinds.setdefault(kind, {"launches": 0, "units": 0, "ms": 0.0})
-            d["launches"] += nl
-            d["units"] += units
-            d["ms"] += ms
-            d["targets_per_search"] = d.get("targets_per_search", 0) + units / max(nl, 1)
-        return kinds
-    kinds = by_kind(recs)
-    # per kind and level: one more step, after the timed region, with every
-    # kind timed
-    _, all_recs, _ = one_step(profile=tuple(vi.KERNEL_KINDS.values()))
-    by_level = {}
-    for kind, lvl, units, ms, nl in all_recs:
-        key = f"{kind}@L{lvl}"
-        by_level[key] = round(by_level.get(key, 0.0) + ms, 3)
-    pas = kinds.get("pass", {"launches": 1, "units": 0, "ms": 1.0, "targets_per_search": 0})
-    avg_ms = pas["ms"] / pas["launches"]
-    # algorithmic bytes per launch: one candidate patch (125 voxels x 5
-    # bytes) per distance the launch computes, and the shift-map state of
-    # every target it processes (units of a pass record = targets x passes)
-    evals_per_launch = pass_evals / pas["launches"]
-    targets_per_launch = pas["units"] / pas["launches"]
-    bytes_per_launch = BYTES_PER_EVAL * evals_per_launch + BYTES_PER_TARGET_PASS * targets_per_launch
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    # nominal evaluations of the passes: all of a step's minus one per target
-    # per search (step 0); the onion peel's share (< 1 %) is included
-    nominal_pass_per_launch = (nominal - pas["targets_per_search"]) / pas["launches"]
-    traffic = None
-    hbm_gbs = None
-    achievable = None
-    if os.path.exists(COUNTERS_JSON):
-        cj = json.load(open(COUNTERS_JSON))
-        if cj.get("source_sha256") == kernel_source_hash() and cj.get("workload") == a.config:
-            traffic = cj["hbm_bytes_per_launch"]
-            hbm_gbs = traffic / (cj["mean_launch_us"] * 1e-6) / 1e9
-        # the rate a plain device copy reaches on the box (read + written),
-        # a property of the hardware, not of the kernel
-        cc = cj.get("copy_calibration")
-        if cc and cc.get("mean_us"):
-            achievable = 2.0 * cc["bytes"] / (cc["mean_us"] * 1e-6) / 1e9
-    roofline = {
-        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-        "kernel": "k_pass<false> (propagation pass with fused random search)",
-        "avg_launch_ms": round(avg_ms, 5), "launches": pas["launches"],
-        "evals_per_launch": round(evals_per_launch, 1),
-        "targets_per_launch": round(targets_per_launch, 1),
-        "algorithmic_bytes_per_launch": round(bytes_per_launch),
-        "nominal_evals_per_launch": round(nominal_pass_per_launch, 1),
-        "nominal_gather_gbs": round(BYTES_PER_EVAL * nominal_pass_per_launch
-                                    / (avg_ms * 1e-3) / 1e9, 1),
-        "measured_hbm_gbs": None if hbm_gbs is None else round(hbm_gbs, 1),
-        "achievable_copy_gbs": None if achievable is None else round(achievable, 1),
-        "frac_of_achievable": None if achievable is None else round(achieved / achievable, 4),
-    }
+    m = measure_plain(a.config, a.steps, a.warmup, a.em_iters)
+    clip, levels = m.pop("clip")
     line = {
         "metric": "NNF patch-distance evals/s (nominal)",
-        "value": nominal / elapsed,
+        "value": m["value"],
         "unit": "evals/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": f"{a.config} plain run {W}x{H}x{T}, {levels}-level pyramid, "
-                               f"5x5x5 patches, {a.em_iters} EM iterations per level, one clip "
-                               "per step",
-                   "global_batch": 1},
-        "clips_per_s": a.steps / elapsed,
-        "latency_p50_ms": 1000 * statistics.median(lat),
-        "latency_p99_ms": 1000 * max(lat),
-        "effective_evals_per_s": effective / elapsed,
-        "kernel_ms_per_step": {k: round(v["ms"], 3) for k, v in by_kind(all_recs).items()},
-        "kernel_ms_per_step_by_level": by_level,
-        "roofline": roofline,
+        "config": {"workload": m["workload"], "global_batch": 1},
+        "clips_per_s": m["clips_per_s"],
+        "latency_p50_ms": m["latency_p50_ms"],
+        "latency_p99_ms": m["latency_p99_ms"],
+        "latency_samples": m["latency_samples"],
+        "effective_evals_per_s": m["effective_evals_per_s"],
+        "kernel_ms_per_step": m["kernel_ms_per_step"],
+        "kernel_ms_per_step_by_level": m["kernel_ms_per_step_by_level"],
+        "roofline": m["roofline"],
         "cpu_baseline": None,
     }
+    sd_clip = None
+    if not a.no_sd and a.config != "sd":
+        s = measure_plain("sd", a.sd_steps, 1, a.em_iters)
+        sd_clip = s.pop("clip")
+        line["sd"] = {k: s[k] for k in ("workload", "value", "ms_per_step", "clips_per_s",
+                                        "latency_p50_ms", "effective_evals_per_s",
+                                        "kernel_ms_per_step")}
+        line["sd"]["roofline"] = {k: s["roofline"][k] for k in
+                                  ("bound", "achieved", "peak", "unit", "frac", "traffic",
+                                   "avg_launch_ms", "algorithmic_frac_of_hbm_peak", "counters")}
+        line["sd"]["ms_per_step_service"] = s["latency_p50_ms"]
+    elif a.config == "sd":
+        sd_clip = (clip, levels)
     if not a.no_batched or not a.no_served:
         bclips = gen_batch_clips(a.batch_clips)
         bres, service = batched_vs_serial(bclips, a.em_iters)
@@ -563,14 +712,17 @@ def main():
             line["batched"] = bres
         if not a.no_served:
             log(f"served: {a.served_seconds} s Poisson trace")
-            # service time of the SD clip alone = this run's SD step latency
             svc = {i: service[i] for i in range(len(bclips))}
-            svc[-1] = statistics.median(lat)
-            line["served"] = served(bclips, (clip.occluded_input(), clip.mask, levels),
+            if sd_clip is None:
+                sd_clip = make_clip("sd")
+            svc[-1] = (line["sd"]["ms_per_step_service"] / 1000.0 if "sd" in line
+                       else m["latency_p50_ms"] / 1000.0)
+            c, L = sd_clip
+            line["served"] = served(bclips, (c.occluded_input(), c.mask, L),
                                     a.served_seconds, a.served_rate, a.em_iters, svc)
     if not a.no_cpu_baseline:
-        log("cpu baseline: oracle search")
-        line["cpu_baseline"] = cpu_baseline(clip, levels, a.em_iters, a.cpu_level, a.cpu_searches)
+        log("cpu baseline: oracle search on a sample of the finest level")
+        line["cpu_baseline"] = cpu_baseline(a.config, a.cpu_frames, a.cpu_frames_1core)
     print(json.dumps(line), flush=True)
 
 
