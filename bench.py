@@ -69,6 +69,10 @@ def parse():
     ap.add_argument("--batch-clips", type=int, default=64)
     ap.add_argument("--served-seconds", type=float, default=30.0)
     ap.add_argument("--served-rate", type=float, default=4.0)
+    ap.add_argument("--served-sweep", metavar="RATES",
+                    help="comma-separated arrival rates (jobs/s; 0 = all jobs at once): served "
+                         "against serial FIFO on Poisson traces of --served-jobs jobs, then exit")
+    ap.add_argument("--served-jobs", type=int, default=240)
     ap.add_argument("--summarize-counters", metavar="DIR",
                     help="summarise a rocprofv3 --output-format csv directory and exit")
     ap.add_argument("--assemble-counters", nargs=5,
@@ -359,6 +363,77 @@ def served(clips, sd_clip, seconds, rate, em_iters, service_alone):
             "serial_fifo_device_resident_p99_s": percentile(serial_dev, 0.99),
             "max_running": srv.max_running, "steps": srv.steps,
             "max_admitted_gb": srv.max_admitted_bytes / 2 ** 30}
+
+
+def served_sweep(rates, n_jobs, em_iters):
+    """Served capacity: for each arrival rate, a Poisson trace of n_jobs jobs
+    (90 % batch-mix clips, 10 % SD) through the continuous-batching server,
+    against serial FIFO execution of the same trace with each clip's serial
+    service time through host memory.  Rate 0: every job arrives at once
+    (the server's and the serial path's throughput at saturation)."""
+    import threading
+    import numpy as np
+    import torch
+    from paper_1503_05528_amd.serve import GpuEngine, Request, Server, fifo_latencies
+    bclips = gen_batch_clips(64)
+    sd, L = make_clip("sd")
+    sd_clip = (sd.occluded_input(), sd.mask, L)
+    log("served sweep: serial service times through host memory")
+    svc = host_service_times(bclips, sd_clip, [-1] + list(range(len(bclips))), em_iters)
+    rows = []
+    for rate in rates:
+        rng = np.random.default_rng(2000 + int(rate * 10))
+        t, jobs = 0.0, []
+        for _ in range(n_jobs):
+            if rate > 0:
+                t += rng.exponential(1.0 / rate)
+            jobs.append((t, -1 if rng.uniform() < 0.10 else int(rng.integers(0, len(bclips)))))
+        free = torch.cuda.mem_get_info()[0]
+        lanes = [GpuEngine(), GpuEngine()]
+        srv = Server(lanes, hbm_budget=int(0.8 * free), max_slots=256,
+                     route=lambda r: 1 if r.mask.size > 20_000_000 else 0)
+
+        def req(idx):
+            v, m, Lv = sd_clip if idx < 0 else bclips[idx]
+            return Request(v, m, dict(levels=Lv, em_tol=-1.0, em_max_iters=em_iters, seed=1),
+                           hole_fraction=float(m.mean()))
+        log(f"served sweep: {n_jobs} jobs at {rate} jobs/s")
+        srv.start()
+        t0 = time.perf_counter()
+        futs = []
+
+        def feeder():
+            for (ta, idx) in jobs:
+                d = t0 + ta - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                r = req(idx)
+                r.arrival = t0 + ta
+                futs.append(srv.submit(r))
+        th = threading.Thread(target=feeder)
+        th.start()
+        th.join()
+        for f in futs:
+            f.result()
+        t_end = time.perf_counter()
+        srv.stop()
+        for e in lanes:
+            e.close()
+        lat = sorted(r.latency for r in srv.records if r.ok)
+        arrivals = [ta for ta, _ in jobs]
+        serial = fifo_latencies(arrivals, [svc[idx] for _, idx in jobs])
+        serial_end = max(a + l for a, l in zip(arrivals, serial))
+        rows.append({
+            "rate_per_s": rate, "jobs": n_jobs, "sd_jobs": sum(1 for _, i in jobs if i < 0),
+            "served_clips_per_s": n_jobs / (t_end - t0),
+            "served_p50_s": percentile(lat, 0.5), "served_p99_s": percentile(lat, 0.99),
+            "serial_clips_per_s": n_jobs / serial_end,
+            "serial_p50_s": percentile(serial, 0.5), "serial_p99_s": percentile(serial, 0.99),
+            "max_running": srv.max_running, "steps": srv.steps})
+        log(json.dumps(rows[-1]))
+    mean_svc = sum(svc[i] for i in range(len(bclips))) * 0.9 / len(bclips) + 0.1 * svc[-1]
+    return {"served_sweep": rows, "serial_capacity_clips_per_s": 1.0 / mean_svc,
+            "mean_serial_service_s": mean_svc}
 
 
 def make_clip(name):
@@ -666,6 +741,10 @@ def main():
         return
 
     vi.lib()
+    if a.served_sweep:
+        rates = [float(r) for r in a.served_sweep.split(",")]
+        print(json.dumps(served_sweep(rates, a.served_jobs, a.em_iters)), flush=True)
+        return
     m = measure_plain(a.config, a.steps, a.warmup, a.em_iters)
     clip, levels = m.pop("clip")
     line = {
