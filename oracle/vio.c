@@ -71,6 +71,7 @@ int vio_params_default(vio_params* o) {
   o->em_tol = 0.1;
   o->recon_mode = VIO_RECON_WEIGHTED;
   o->seed = 0;
+  o->temporal_subsample = 0;
   return VIO_OK;
 }
 
@@ -191,7 +192,8 @@ static int alloc_level(level_t* L, int32_t W, int32_t H, int32_t T) {
 /* ------------------------------------------------------------------------ */
 /* Pyramids (Alg. 4 first lines; Sec. 3.3 Eqs. (3.5), (3.7); Sec. 3.6).     */
 /* Image pyramid: 2x2 spatial box mean rounded half up, no temporal         */
-/* subsampling.  Occlusion pyramid: OR over the 2x2 block.  Texture T at    */
+/* subsampling (2x2x2 blocks and T^l(x,y,t) = T(2^l x, 2^l y, 2^l t) when   */
+/* temporal_subsample is set).  Occlusion pyramid: OR over the 2x2 block.  Texture T at    */
 /* the finest level: mean over the square nu (side 2^(L-1), anchored at the */
 /* pixel) of |grey(x+1)-grey(x-1)| resp. along y, with grey = (R+G+B)/3,     */
 /* known pixels only; coarser levels subsample it: T^l(x,y,t)=T(2^l x,2^l y,t). */
@@ -258,22 +260,25 @@ int vio_create(vio_ctx** out, const vio_params* prm, int32_t W, int32_t H, int32
   if (prm->n_jf < 0 || prm->n_jf > 8 || prm->pm_iters < 0 || prm->lambda < 0) return VIO_E_INVAL;
   if (prm->recon_mode != VIO_RECON_WEIGHTED && prm->recon_mode != VIO_RECON_MEAN)
     return VIO_E_INVAL;
+  if (prm->temporal_subsample != 0 && prm->temporal_subsample != 1) return VIO_E_INVAL;
   vio_ctx* ctx = (vio_ctx*)calloc(1, sizeof(vio_ctx));
   if (!ctx) return VIO_E_NOMEM;
   ctx->prm = *prm;
   ctx->L = prm->levels;
-  int32_t w = W, h = H;
+  const int ts = prm->temporal_subsample;
+  int32_t w = W, h = H, tl = T;
   for (int l = 0; l < ctx->L; ++l) {
-    if (w < prm->patch[0] || h < prm->patch[1] || T < prm->patch[2]) {
+    if (w < prm->patch[0] || h < prm->patch[1] || tl < prm->patch[2]) {
       vio_destroy(ctx);
       return VIO_E_INVAL;
     }
-    if (alloc_level(&ctx->lv[l], w, h, T) != VIO_OK) {
+    if (alloc_level(&ctx->lv[l], w, h, tl) != VIO_OK) {
       vio_destroy(ctx);
       return VIO_E_NOMEM;
     }
     w = (w + 1) / 2;
     h = (h + 1) / 2;
+    if (ts) tl = (tl + 1) / 2;
   }
   /* level 0: the input, zero under the hole (those values are never read) */
   level_t* L0 = &ctx->lv[0];
@@ -292,15 +297,17 @@ int vio_create(vio_ctx** out, const vio_params* prm, int32_t W, int32_t H, int32
           int64_t i = lin(C, x, y, t);
           int any = 0, cnt = 0;
           int sum[3] = {0, 0, 0};
-          for (int by = 0; by < 2; ++by)
-            for (int bx = 0; bx < 2; ++bx) {
-              int32_t fx = 2 * x + bx, fy = 2 * y + by;
-              if (fx >= F->W || fy >= F->H) continue;
-              int64_t j = lin(F, fx, fy, t);
-              any |= F->hole[j];
-              cnt++;
-              for (int c = 0; c < 3; ++c) sum[c] += F->rgbt[5 * j + c];
-            }
+          /* the in-volume 2x2 block (2x2x2 with temporal subsampling) */
+          for (int bt = 0; bt < (ts ? 2 : 1); ++bt)
+            for (int by = 0; by < 2; ++by)
+              for (int bx = 0; bx < 2; ++bx) {
+                int32_t fx = 2 * x + bx, fy = 2 * y + by, ft = ts ? 2 * t + bt : t;
+                if (fx >= F->W || fy >= F->H || ft >= F->T) continue;
+                int64_t j = lin(F, fx, fy, ft);
+                any |= F->hole[j];
+                cnt++;
+                for (int c = 0; c < 3; ++c) sum[c] += F->rgbt[5 * j + c];
+              }
           C->hole[i] = (uint8_t)any;
           for (int c = 0; c < 3; ++c)
             C->rgbt[5 * i + c] = (uint8_t)(any ? 0 : (sum[c] + cnt / 2) / cnt);
@@ -321,7 +328,7 @@ int vio_create(vio_ctx** out, const vio_params* prm, int32_t W, int32_t H, int32
       for (int32_t y = 0; y < C->H; ++y)
         for (int32_t x = 0; x < C->W; ++x) {
           int64_t i = lin(C, x, y, t);
-          int64_t j = lin(L0, (int64_t)x << l, (int64_t)y << l, t);
+          int64_t j = lin(L0, (int64_t)x << l, (int64_t)y << l, ts ? (int64_t)t << l : t);
           C->rgbt[5 * i + 3] = C->hole[i] ? 0 : Tx[j];
           C->rgbt[5 * i + 4] = C->hole[i] ? 0 : Ty[j];
         }
@@ -858,9 +865,9 @@ int vio_onion_init(vio_ctx* ctx, int32_t* layers_run) {
 
 /* ------------------------------------------------------------------------ */
 /* Level transition (Sec. 3.6): nearest-neighbour upsampling of the shift   */
-/* map (spatial components doubled, temporal unchanged since time is not    */
-/* subsampled); the fine target inherits its parent's distance and count;   */
-/* then the finer hole is reconstructed.                                    */
+/* map (spatial components doubled; the temporal one kept, or doubled too   */
+/* with temporal subsampling); the fine target inherits its parent's        */
+/* distance and count; then the finer hole is reconstructed.                */
 /* ------------------------------------------------------------------------ */
 int vio_transition(vio_ctx* ctx, int32_t level) {
   if (!ctx || level < 0 || level + 1 >= ctx->L) return VIO_E_INVAL;
@@ -875,10 +882,14 @@ int vio_transition(vio_ctx* ctx, int32_t level) {
           F->cand[i] = -1; F->dist[i] = -1; F->nvox[i] = 0;
           continue;
         }
-        int64_t P = lin(C, x / 2, y / 2, t);
+        const int ts = ctx->prm.temporal_subsample;
+        const int32_t Pt = ts ? t / 2 : t;
+        int64_t P = lin(C, x / 2, y / 2, Pt);
         int32_t cx, cy, ct;
         unlin(C, C->cand[P], &cx, &cy, &ct);
-        int32_t fx = x + 2 * (cx - x / 2), fy = y + 2 * (cy - y / 2), ft = t + (ct - t);
+        /* the parent's shift, doubled along every subsampled axis */
+        int32_t fx = x + 2 * (cx - x / 2), fy = y + 2 * (cy - y / 2);
+        int32_t ft = ts ? t + 2 * (ct - Pt) : t + (ct - t);
         F->cand[i] = (int32_t)lin(F, fx, fy, ft);
         F->dist[i] = C->dist[P];
         F->nvox[i] = C->nvox[P];

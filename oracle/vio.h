@@ -50,6 +50,9 @@ typedef struct {
   double em_tol;        /* 0.1, mean absolute colour change; < 0: run em_max_iters */
   int32_t recon_mode;   /* VIO_RECON_WEIGHTED or VIO_RECON_MEAN */
   uint64_t seed;        /* Philox key word 0 */
+  int32_t temporal_subsample; /* 0: coarser levels keep every frame (Sec. 3.6);
+                                 1: each coarser level also halves the frame
+                                 count (2x2x2 blocks) */
 } vio_params;
 
 typedef struct vio_ctx vio_ctx;
