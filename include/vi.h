@@ -67,6 +67,14 @@ typedef struct {
                            VI_RECON_MEAN (s = 1); used by every reconstruction
                            except the final one, which is VI_RECON_BEST */
   uint64_t seed;        /* key of the Philox4x64-10 random numbers */
+  int32_t temporal_subsample; /* 0 (default): coarser levels keep every frame
+                                 (Sec. 3.6); 1: each coarser level also halves
+                                 the frame count (2x2x2 box means and
+                                 OR-pooled occlusion, texture features taken
+                                 at (2^l x, 2^l y, 2^l t), shift maps
+                                 upsampled in time as in space), for objects
+                                 that stay long behind the occlusion; the
+                                 coarsest level must keep >= 5 frames */
 } vi_params;
 
 typedef struct vi_ctx vi_ctx; /* one clip: all its device state */

@@ -180,19 +180,25 @@ vi_status check_params(const vi_params* p) {
   if (p->em_max_iters < 1) return fail(VI_E_INVAL, "em_max_iters must be >= 1");
   if (p->recon_mode != VI_RECON_WEIGHTED && p->recon_mode != VI_RECON_MEAN)
     return fail(VI_E_INVAL, "recon_mode must be WEIGHTED or MEAN");
+  if (p->temporal_subsample != 0 && p->temporal_subsample != 1)
+    return fail(VI_E_INVAL, "temporal_subsample must be 0 or 1");
   return VI_OK;
 }
+
+// frames of the next coarser level
+int32_t coarser_T(const vi_params* p, int32_t T) { return p->temporal_subsample ? (T + 1) / 2 : T; }
 
 vi_status check_dims(const vi_params* p, int32_t W, int32_t H, int32_t T) {
   if (W < 5 || H < 5 || T < 5 || W >= 32768 || H >= 32768 || T >= 32768)
     return fail(VI_E_INVAL, "W, H, T must be in [5, 32768)");
   if ((int64_t)W * H * T >= (int64_t(1) << 31)) return fail(VI_E_INVAL, "W*H*T must be < 2^31");
-  int32_t w = W, h = H;
+  int32_t w = W, h = H, t = T;
   for (int l = 1; l < p->levels; ++l) {
     w = (w + 1) / 2;
     h = (h + 1) / 2;
+    t = coarser_T(p, t);
   }
-  if (w < 5 || h < 5) return fail(VI_E_INVAL, "the coarsest level is smaller than a patch");
+  if (w < 5 || h < 5 || t < 5) return fail(VI_E_INVAL, "the coarsest level is smaller than a patch");
   return VI_OK;
 }
 
@@ -575,6 +581,7 @@ vi_status vi_params_default(vi_params* o) {
   o->em_tol = 0.1;
   o->recon_mode = VI_RECON_WEIGHTED;
   o->seed = 0;
+  o->temporal_subsample = 0;
   return VI_OK;
 }
 
@@ -585,10 +592,10 @@ size_t vi_footprint_bytes(const vi_params* prm, int32_t W, int32_t H, int32_t T,
   if (check_params(prm) != VI_OK || check_dims(prm, W, H, T) != VI_OK) return 0;
   if (!(hole_fraction >= 0.0 && hole_fraction <= 1.0)) return 0;
   size_t total = 0;
-  int64_t w = W, h = H;
+  int64_t w = W, h = H, t = T;
   const int64_t V0 = (int64_t)W * H * T;
   for (int l = 0; l < prm->levels; ++l) {
-    const int64_t V = w * h * T;
+    const int64_t V = w * h * t;
     // vox 8, hole/dsrc/htil 3, nnf 16, nvox 1, change marks 3, source list 4
     total += (size_t)V * 35;
     // target and hole lists: the dilated hole is at most 125x the hole
@@ -596,6 +603,7 @@ size_t vi_footprint_bytes(const vi_params* prm, int32_t W, int32_t H, int32_t T,
     total += (size_t)((double)V * (fr + hole_fraction) * 4.0) + 4096;
     w = (w + 1) / 2;
     h = (h + 1) / 2;
+    t = coarser_T(prm, (int32_t)t);
   }
   // creation temporaries at the finest level: gradients 4, box sums 8,
   // dilation scratch 2, compaction list 4
@@ -628,14 +636,14 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
     return s;
   };
   // level geometry and buffers
-  int32_t w = W, h = H;
+  int32_t w = W, h = H, tl = T;
   for (int l = 0; l < c->L; ++l) {
     vi::DevLevel& d = c->lv[l].d;
     d.W = w;
     d.H = h;
-    d.T = T;
+    d.T = tl;
     d.WH = w * h;
-    d.V = w * h * T;
+    d.V = w * h * tl;
     d.level = l;
     d.fdW = vi::make_fastdiv((uint32_t)w);
     d.fdWH = vi::make_fastdiv((uint32_t)(w * h));
@@ -658,6 +666,7 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
     d.repoch = 1;
     w = (w + 1) / 2;
     h = (h + 1) / 2;
+    tl = coarser_T(prm, tl);
   }
   const vi::DevLevel& L0 = c->lv[0].d;
   const size_t V0 = (size_t)L0.V;

@@ -1095,13 +1095,18 @@ __global__ void k_upsample(DevLevel F, DevLevel C, const int32_t* __restrict__ f
   const int32_t p = ftlist[i];
   int32_t x, y, t;
   unlin(F, p, x, y, t);
-  const int32_t P = (t * C.H + (y >> 1)) * C.W + (x >> 1);
+  // with temporal subsampling (the coarser level holds fewer frames) the
+  // parent and the doubled shift cover time as well
+  const bool ts = C.T != F.T;
+  const int32_t Pt = ts ? t >> 1 : t;
+  const int32_t P = (Pt * C.H + (y >> 1)) * C.W + (x >> 1);
   const int2 pc = C.nnf0[P];
   int32_t cx, cy, ct;
   unlin(C, pc.x, cx, cy, ct);
   const int32_t fx = x + 2 * (cx - (x >> 1));
   const int32_t fy = y + 2 * (cy - (y >> 1));
-  F.nnf0[p] = make_int2((ct * F.H + fy) * F.W + fx, pc.y);
+  const int32_t ft = ts ? t + 2 * (ct - Pt) : ct;
+  F.nnf0[p] = make_int2((ft * F.H + fy) * F.W + fx, pc.y);
   F.nvox[p] = C.nvox[P];
 }
 
@@ -1128,18 +1133,21 @@ __global__ void k_pyr_down(DevLevel F, DevLevel C) {
   unlin(C, i, x, y, t);
   int any = 0, cnt = 0;
   uint32_t sr = 0, sg = 0, sb = 0;
-  for (int by = 0; by < 2; ++by)
-    for (int bx = 0; bx < 2; ++bx) {
-      const int32_t fx = 2 * x + bx, fy = 2 * y + by;
-      if (fx >= F.W || fy >= F.H) continue;
-      const int32_t j = (t * F.H + fy) * F.W + fx;
-      any |= F.hole[j];
-      ++cnt;
-      const uint32_t v = F.vox[j].x;
-      sr += v & 255;
-      sg += (v >> 8) & 255;
-      sb += (v >> 16) & 255;
-    }
+  // 2x2 blocks, or 2x2x2 when the coarser level holds fewer frames
+  const int nbt = C.T != F.T ? 2 : 1;
+  for (int bt = 0; bt < nbt; ++bt)
+    for (int by = 0; by < 2; ++by)
+      for (int bx = 0; bx < 2; ++bx) {
+        const int32_t fx = 2 * x + bx, fy = 2 * y + by, ft = nbt == 2 ? 2 * t + bt : t;
+        if (fx >= F.W || fy >= F.H || ft >= F.T) continue;
+        const int32_t j = (ft * F.H + fy) * F.W + fx;
+        any |= F.hole[j];
+        ++cnt;
+        const uint32_t v = F.vox[j].x;
+        sr += v & 255;
+        sg += (v >> 8) & 255;
+        sb += (v >> 16) & 255;
+      }
   C.hole[i] = (uint8_t)any;
   uint32_t out = 0;
   if (!any) {
@@ -1202,9 +1210,11 @@ __global__ void k_tex_level(const uint2* __restrict__ hsum, DevLevel L0, DevLeve
   if (i >= Ll.V) return;
   uint32_t tx = 0, ty = 0;
   if (!Ll.hole[i]) {
-    int32_t X, Y, t;
-    unlin(Ll, i, X, Y, t);
-    const int32_t x = X << l, y = Y << l;
+    int32_t X, Y, tl;
+    unlin(Ll, i, X, Y, tl);
+    // the finest level's features at (2^l x, 2^l y, t), or 2^l t as well
+    // when the pyramid subsamples time
+    const int32_t x = X << l, y = Y << l, t = Ll.T != L0.T ? tl << l : tl;
     uint64_t sx = 0, cx = 0, sy = 0, cy = 0;
     const int32_t e = min(L0.H, y + s);
     for (int32_t yy = y; yy < e; ++yy) {

@@ -35,6 +35,7 @@ class Params(C.Structure):
         ("em_tol", C.c_double),
         ("recon_mode", C.c_int32),
         ("seed", C.c_uint64),
+        ("temporal_subsample", C.c_int32),
     ]
 
 

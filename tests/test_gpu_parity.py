@@ -299,3 +299,71 @@ def test_onion_layers_teacher_forced(vi, name, mode):
         Hp = E
         layer += 1
     assert layer >= 2
+
+
+# ---------------------------------------------------------------------------
+# temporally subsampled pyramids (Sec. 3.6): 20 -> 10 -> 5 frames
+# ---------------------------------------------------------------------------
+
+def _temporal_clip():
+    return synth.small(24, 61, 47, 20, levels=3, frac=0.05)
+
+
+def test_temporal_create_matches_oracle(vi):
+    clip = _temporal_clip()
+    o, g = make_pair(vi, clip, levels=3, temporal_subsample=1)
+    for lv in range(3):
+        assert o.info(lv) == g.info(lv)
+        assert o.dims(lv)[2] == (20, 10, 5)[lv]
+        for a, b in zip(o.sets(lv), g.sets(lv)):
+            assert np.array_equal(a, host(b)), lv
+        for a, b in zip(o.get_state(lv), g.get_state(lv)):
+            assert np.array_equal(a, host(b)), lv
+
+
+@pytest.mark.parametrize("em_iter", [0, 2])
+def test_temporal_search_bitexact(vi, em_iter):
+    clip = _temporal_clip()
+    o, g = make_pair(vi, clip, levels=3, seed=7, temporal_subsample=1)
+    for lv in range(3):
+        rgbt, cand = _forced_state(o, lv, 300 + lv)
+        o.set_state(lv, rgbt=rgbt, cand=cand)
+        g.set_state(lv, rgbt=rgbt, cand=cand)
+        o.nnf_search(lv, em_iter)
+        g.nnf_search(lv, em_iter)
+        for a, b in zip(o.get_state(lv)[1:], g.get_state(lv)[1:]):
+            assert np.array_equal(a, host(b)), lv
+
+
+def test_temporal_transition_bitexact(vi):
+    clip = _temporal_clip()
+    o, g = make_pair(vi, clip, levels=3, seed=5, recon_mode=1, temporal_subsample=1)
+    for lv in (2, 1):
+        rgbt, cand = _forced_state(o, lv, 10 + lv)
+        o.set_state(lv, rgbt=rgbt, cand=cand)
+        o.nnf_search(lv, 0)
+        g.set_state(lv, *o.get_state(lv))
+        o.transition(lv - 1)
+        g.transition(lv - 1)
+        for a, b in zip(o.get_state(lv - 1), g.get_state(lv - 1)):
+            assert np.array_equal(a, host(b)), lv
+
+
+def test_temporal_inpaint_mean_end_to_end_bitexact(vi):
+    clip = _temporal_clip()
+    o, g = make_pair(vi, clip, levels=3, seed=12, recon_mode=1, temporal_subsample=1)
+    assert np.array_equal(o.inpaint(), host(g.inpaint()))
+
+
+def test_temporal_weighted_reconstruction_close(vi):
+    clip = _temporal_clip()
+    o, g = make_pair(vi, clip, levels=3, seed=9, temporal_subsample=1)
+    for lv in range(3):
+        rgbt, cand = _forced_state(o, lv, 400 + lv)
+        o.set_state(lv, rgbt=rgbt, cand=cand)
+        o.nnf_search(lv, 0)
+        g.set_state(lv, *o.get_state(lv))
+        oo, _ = o.reconstruct(lv, 0)
+        go, _ = g.reconstruct(lv, 0)
+        hole_idx = np.flatnonzero(o.sets(lv)[0].ravel())
+        assert_recon_close(oo, host(go), o.get_state(lv)[0], host(g.get_state(lv)[0]), hole_idx)
