@@ -626,16 +626,18 @@ def roofline_of(workload, pass_evals, pass_units, pass_ms, pass_launches, nomina
     }
 
 
-def measure_plain(config, steps, warmup, em_iters):
+def measure_plain(config, steps, warmup, em_iters, temporal=False):
     """Whole inpaintings of one clip from inputs resident in HBM: timed
-    steps, per-kind kernel time of one more step, and the roofline record."""
+    steps, per-kind kernel time of one more step, and the roofline record
+    (temporal: pyramids subsampled in time as well)."""
     import torch
     from paper_1503_05528_amd import vi
     clip, levels = make_clip(config)
     W, H, T = clip.shape
     video = torch.from_numpy(clip.occluded_input()).cuda()
     mask = torch.from_numpy(clip.mask).cuda()
-    params = vi.default_params(levels=levels, em_tol=-1.0, em_max_iters=em_iters, seed=1)
+    params = vi.default_params(levels=levels, em_tol=-1.0, em_max_iters=em_iters, seed=1,
+                               temporal_subsample=1 if temporal else 0)
     torch.cuda.synchronize()
 
     def one_step(profile=None):
@@ -693,7 +695,8 @@ def measure_plain(config, steps, warmup, em_iters):
     return {
         "value": nominal / elapsed, "ms_per_step": 1000.0 * elapsed / steps,
         "clips_per_s": steps / elapsed, "steps": steps, "warmup": warmup,
-        "workload": f"{config} plain run {W}x{H}x{T}, {levels}-level pyramid, 5x5x5 patches, "
+        "workload": f"{config} plain run {W}x{H}x{T}, {levels}-level pyramid"
+                    f"{' subsampled in time as well' if temporal else ''}, 5x5x5 patches, "
                     f"{em_iters} EM iterations per level, one clip per step",
         "latency_p50_ms": 1000 * percentile(lat, 0.5),
         "latency_p99_ms": 1000 * percentile(lat, 0.99),
@@ -784,6 +787,12 @@ def main():
         line["sd"]["ms_per_step_service"] = s["latency_p50_ms"]
     elif a.config == "sd":
         sd_clip = (clip, levels)
+    if not a.no_sd:
+        # the SD clip with temporally subsampled pyramids (Sec. 3.6)
+        s = measure_plain("sd", a.sd_steps, 1, a.em_iters, temporal=True)
+        s.pop("clip")
+        line["sd_temporal"] = {k: s[k] for k in ("workload", "value", "ms_per_step",
+                                                 "clips_per_s", "kernel_ms_per_step")}
     if not a.no_batched or not a.no_served:
         bclips = gen_batch_clips(a.batch_clips)
         bres, service = batched_vs_serial(bclips, a.em_iters)
