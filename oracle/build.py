@@ -12,10 +12,10 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    src = os.path.join(HERE, "vio.c")
+    srcs = [os.path.join(HERE, f) for f in ("vio.c", "vio_align.c")]
     tmp = LIB + ".tmp"
     cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-           "-Wall", "-Wextra", "-Wno-unused-parameter", src, "-o", tmp, "-lm"]
+           "-Wall", "-Wextra", "-Wno-unused-parameter", *srcs, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)

@@ -135,6 +135,38 @@ int vio_transition(vio_ctx* ctx, int32_t level);
 /* The whole method minus realignment: out_rgb [T][H][W][3]. */
 int vio_inpaint(vio_ctx* ctx, uint8_t* out_rgb);
 
+/* ---- Realignment of a video with a moving camera (Sec. 3.4, Alg. 2) ----
+ * Affine maps are 6 doubles m: x' = m0 x + m1 y + m2, y' = m3 x + m4 y + m5,
+ * in pixel coordinates of a frame (x right, y down). */
+typedef struct {
+  int32_t levels; /* grey pyramid levels of the motion estimation, 3 */
+  int32_t iters;  /* robust Gauss-Newton steps per level, 8 */
+  double tukey_c; /* Tukey biweight constant, grey levels (0..255), 20 */
+} vio_align_params;
+int vio_align_params_default(vio_align_params* out);
+/* The dominant affine motion of every pair of successive frames (Alg. 2,
+ * first loop): theta [T-1][6], theta_n maps frame n's pixels to their
+ * positions in frame n+1.  rgb [T][H][W][3]; mask [T][H][W] nonzero =
+ * occluded (excluded from the estimation). */
+int vio_align_estimate(const uint8_t* rgb, const uint8_t* mask, int32_t W, int32_t H,
+                       int32_t T, const vio_align_params* prm, double* theta);
+/* Composition to the reference frame T/2 (0-based; Alg. 2, second loop):
+ * M [T][6], M_n maps frame n's pixels to the reference frame. */
+int vio_align_compose(const double* theta, int32_t T, double* M);
+/* inverse of an affine map (VIO_E_INVAL if singular) */
+int vio_affine_inverse(const double m[6], double inv[6]);
+/* The aligned video (Alg. 2, AffineWarp): pixel y of aligned frame n is
+ * frame n sampled at M_n^-1(y) by bilinear interpolation, rounded half up;
+ * out_mask = 1 (and out_rgb 0) where a neighbour of nonzero weight lies
+ * outside the frame or is occluded. */
+int vio_align_warp(const uint8_t* rgb, const uint8_t* mask, int32_t W, int32_t H, int32_t T,
+                   const double* M, uint8_t* out_rgb, uint8_t* out_mask);
+/* The inverse (Alg. 4, last step): out_rgb = rgb, except every occluded
+ * pixel x of mask, which takes the aligned video sampled at M_n(x) (clamped
+ * to the frame) by bilinear interpolation. */
+int vio_align_unwarp(const uint8_t* aligned, const uint8_t* rgb, const uint8_t* mask, int32_t W,
+                     int32_t H, int32_t T, const double* M, uint8_t* out_rgb);
+
 /* E = sum over H~^level of SSD(q, cand(q)) (unnormalised). */
 int64_t vio_energy(const vio_ctx* ctx, int32_t level);
 

@@ -36,6 +36,10 @@ class Params(C.Structure):
     ]
 
 
+class AlignParams(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("iters", C.c_int32), ("tukey_c", C.c_double)]
+
+
 def lib():
     global _LIB
     if _LIB is None:
@@ -74,6 +78,14 @@ def lib():
         L.vio_energy.argtypes = [C.c_void_p, C.c_int32]
         L.vio_energy.restype = C.c_int64
         L.vio_num_threads.argtypes = []
+        f64p = P(C.c_double)
+        L.vio_align_params_default.argtypes = [P(AlignParams)]
+        L.vio_align_estimate.argtypes = [u8p, u8p, C.c_int32, C.c_int32, C.c_int32,
+                                         P(AlignParams), f64p]
+        L.vio_align_compose.argtypes = [f64p, C.c_int32, f64p]
+        L.vio_affine_inverse.argtypes = [f64p, f64p]
+        L.vio_align_warp.argtypes = [u8p, u8p, C.c_int32, C.c_int32, C.c_int32, f64p, u8p, u8p]
+        L.vio_align_unwarp.argtypes = [u8p, u8p, u8p, C.c_int32, C.c_int32, C.c_int32, f64p, u8p]
         _LIB = L
     return _LIB
 
@@ -264,3 +276,59 @@ class Oracle:
 
 def num_threads():
     return int(lib().vio_num_threads())
+
+
+# ---------------------------------------------------------------- realignment
+
+def align_params(**kw) -> AlignParams:
+    p = AlignParams()
+    _check("vio_align_params_default", lib().vio_align_params_default(C.byref(p)))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def align_estimate(video, mask, **kw):
+    """theta [T-1][6]: the dominant affine motion of every frame pair."""
+    v = np.ascontiguousarray(video, np.uint8)
+    m = np.ascontiguousarray(mask, np.uint8)
+    T, H, W, _ = v.shape
+    th = np.zeros((T - 1, 6), np.float64)
+    p = align_params(**kw)
+    _check("vio_align_estimate", lib().vio_align_estimate(
+        _ptr(v, C.c_uint8), _ptr(m, C.c_uint8), W, H, T, C.byref(p), _ptr(th, C.c_double)))
+    return th
+
+
+def align_compose(theta, T):
+    th = np.ascontiguousarray(theta, np.float64)
+    M = np.zeros((T, 6), np.float64)
+    _check("vio_align_compose", lib().vio_align_compose(_ptr(th, C.c_double), T,
+                                                        _ptr(M, C.c_double)))
+    return M
+
+
+def align_warp(video, mask, M):
+    v = np.ascontiguousarray(video, np.uint8)
+    m = np.ascontiguousarray(mask, np.uint8)
+    T, H, W, _ = v.shape
+    Mm = np.ascontiguousarray(M, np.float64)
+    out = np.zeros_like(v)
+    om = np.zeros_like(m)
+    _check("vio_align_warp", lib().vio_align_warp(
+        _ptr(v, C.c_uint8), _ptr(m, C.c_uint8), W, H, T, _ptr(Mm, C.c_double),
+        _ptr(out, C.c_uint8), _ptr(om, C.c_uint8)))
+    return out, om
+
+
+def align_unwarp(aligned, video, mask, M):
+    a = np.ascontiguousarray(aligned, np.uint8)
+    v = np.ascontiguousarray(video, np.uint8)
+    m = np.ascontiguousarray(mask, np.uint8)
+    T, H, W, _ = v.shape
+    Mm = np.ascontiguousarray(M, np.float64)
+    out = np.zeros_like(v)
+    _check("vio_align_unwarp", lib().vio_align_unwarp(
+        _ptr(a, C.c_uint8), _ptr(v, C.c_uint8), _ptr(m, C.c_uint8), W, H, T,
+        _ptr(Mm, C.c_double), _ptr(out, C.c_uint8)))
+    return out

@@ -244,6 +244,70 @@ def small(seed: int, W: int, H: int, T: int, frac: float = 0.04, levels: int = 2
     return Clip(f"small{seed}", vid, mask, levels, seed)
 
 
+def jittered(seed: int = 4, W: int = 320, H: int = 240, T: int = 24, n_obj: int = 3,
+             max_rot_deg: float = 0.6, max_scale: float = 0.012, max_shift: float = 3.0,
+             sigma: float = 2.0, hole_frac: float = 0.04):
+    """A scene filmed by a shaking camera: a static grating background and
+    textured ellipses moving in world coordinates, seen through a random
+    affine camera per frame (rotation, scale and translation about the frame
+    centre).  Returns (clip, cams): cams [T][6] maps a frame's pixel (x, y)
+    to world coordinates, w = (c0 x + c1 y + c2, c3 x + c4 y + c5).  The
+    occlusion is a world-fixed ellipse seen through the same cameras.  Every
+    pixel is rendered from the scene at its world position (no resampling
+    of other frames)."""
+    rng = np.random.default_rng(seed)
+    n_grat = 6
+    f = rng.uniform(1 / 64, 1 / 10, n_grat)
+    th = rng.uniform(0, np.pi, n_grat)
+    ph = rng.uniform(0, 2 * np.pi, n_grat)
+    A = rng.uniform(10, 25, n_grat)
+    g = rng.uniform(0.5, 1.0, (n_grat, 3))
+    cx, cy = (W - 1) / 2.0, (H - 1) / 2.0
+    cams = np.zeros((T, 6))
+    for t in range(T):
+        a = np.deg2rad(rng.uniform(-max_rot_deg, max_rot_deg))
+        sc = 1.0 + rng.uniform(-max_scale, max_scale)
+        tx, ty = rng.uniform(-max_shift, max_shift, 2)
+        c, sn = sc * np.cos(a), sc * np.sin(a)
+        # w = R (x - centre) + centre + shift
+        cams[t] = (c, -sn, cx - c * cx + sn * cy + tx, sn, c, cy - sn * cx - c * cy + ty)
+    objs = []
+    for _ in range(n_obj):
+        a_ = int(rng.integers(8, 24))
+        b_ = int(rng.integers(8, 24))
+        sp = rng.uniform(0.5, 2.0)
+        ang = rng.uniform(0, 2 * np.pi)
+        objs.append((a_, b_, sp * np.cos(ang), sp * np.sin(ang), rng.uniform(0, W),
+                     rng.uniform(0, H), rng.integers(0, 256, (2 * b_ + 1, 2 * a_ + 1, 3))))
+    ha = np.sqrt(hole_frac * W * H * 1.3 / np.pi)
+    hb = hole_frac * W * H / (np.pi * ha)
+    hx, hy = rng.uniform(0.35 * W, 0.65 * W), rng.uniform(0.35 * H, 0.65 * H)
+    y, x = np.meshgrid(np.arange(H, dtype=np.float64), np.arange(W, dtype=np.float64),
+                       indexing="ij")
+    vid = np.empty((T, H, W, 3), np.uint8)
+    mask = np.zeros((T, H, W), np.uint8)
+    for t in range(T):
+        c0, c1, c2, c3, c4, c5 = cams[t]
+        wx = c0 * x + c1 * y + c2
+        wy = c3 * x + c4 * y + c5
+        acc = np.full((H, W, 3), 128.0)
+        for i in range(n_grat):
+            sgr = np.sin(2 * np.pi * f[i] * (np.cos(th[i]) * wx + np.sin(th[i]) * wy) + ph[i])
+            acc += A[i] * sgr[..., None] * g[i][None, None, :]
+        for (a_, b_, vx, vy, ox, oy, tex) in objs:
+            dx = wx - (ox + vx * t)
+            dy = wy - (oy + vy * t)
+            inside = (dx / a_) ** 2 + (dy / b_) ** 2 <= 1.0
+            ix = np.clip(np.floor(dx + 0.5).astype(np.int64) + a_, 0, 2 * a_)
+            iy = np.clip(np.floor(dy + 0.5).astype(np.int64) + b_, 0, 2 * b_)
+            acc[inside] = tex[iy[inside], ix[inside]]
+        if sigma > 0:
+            acc += rng.normal(0.0, sigma, (H, W, 3))
+        vid[t] = _u8(acc)
+        mask[t] = ((wx - hx) / ha) ** 2 + ((wy - hy) / hb) ** 2 <= 1.0
+    return Clip(f"jitter{seed}", vid, mask, 2, seed), cams
+
+
 def served_trace(duration_s: float = 120.0, rate: float = 4.0, seed: int = 2000,
                  sd_frac: float = 0.10):
     """Poisson arrivals: list of (arrival_time_s, kind, seed) where kind is
