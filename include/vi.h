@@ -276,6 +276,54 @@ int32_t vi_batch_size(const vi_batch* b);
  * stay usable); NULL-safe.  Syncs the batch's stream. */
 void vi_batch_destroy(vi_batch* b);
 
+/* ---- Realignment of a video filmed by a moving camera (Sec. 3.4, Alg. 2;
+ * the inverse warp of Alg. 4) ----
+ * An affine map is 6 doubles m in pixel coordinates (x right, y down):
+ * x' = m0 x + m1 y + m2, y' = m3 x + m4 y + m5.  The pipeline: estimate the
+ * dominant motion of every frame pair, compose the maps to the reference
+ * (middle) frame, warp the video and its occlusion to the reference frame,
+ * inpaint the aligned video, unwarp its result into the original occlusion. */
+typedef struct {
+  int32_t levels; /* grey pyramid levels of the motion estimation, 3 */
+  int32_t iters;  /* robust Gauss-Newton steps per level, 8 */
+  double tukey_c; /* Tukey biweight constant in grey levels (0..255), 20 */
+} vi_align_params;
+vi_status vi_align_params_default(vi_align_params* out);
+/* The dominant affine motion of every pair of successive frames (Alg. 2,
+ * first loop; the robust estimator the paper borrows is written out as a
+ * coarse-to-fine, Tukey-weighted Gauss-Newton fit of brightness constancy on
+ * the grey level (R+G+B)/3 over the unoccluded pixels).
+ *   rgb (dev) [T][H][W][3], mask (dev) [T][H][W] (nonzero = occluded,
+ *   excluded), theta (host) [T-1][6]: theta_n maps frame n's pixels to their
+ *   positions in frame n+1.  T >= 2; W, H >= 8 << (levels - 1) roughly (the
+ *   coarsest estimation level must keep 8 x 8 pixels).  Syncs; allocates its
+ *   working memory.  Errors: VI_E_INVAL, VI_E_NOMEM, VI_E_HIP. */
+vi_status vi_align_estimate(const uint8_t* rgb, const uint8_t* mask, int32_t W, int32_t H,
+                            int32_t T, const vi_align_params* prm, double* theta,
+                            void* hip_stream);
+/* Composition to the reference frame T/2 (0-based; Alg. 2, second loop):
+ * M (host) [T][6], M_n maps frame n's pixels to the reference frame (the
+ * identity for the reference; the inverse pair maps after it).  Host only.
+ * Errors: VI_E_INVAL (null pointer, T < 1, a singular map). */
+vi_status vi_align_compose(const double* theta, int32_t T, double* M);
+/* The aligned video (Alg. 2, AffineWarp): pixel y of aligned frame n is
+ * frame n sampled at M_n^-1(y) by bilinear interpolation in double
+ * precision, rounded half up; out_mask (dev) [T][H][W] = 1 (and out_rgb 0)
+ * where a neighbour of nonzero weight is outside the frame or occluded, so
+ * the occlusion is warped with the video.  rgb, mask, out_rgb, out_mask
+ * (dev); M (host) [T][6].  Syncs.  Errors: VI_E_INVAL (null pointer, sizes,
+ * singular map), VI_E_HIP. */
+vi_status vi_align_warp(const uint8_t* rgb, const uint8_t* mask, int32_t W, int32_t H,
+                        int32_t T, const double* M, uint8_t* out_rgb, uint8_t* out_mask,
+                        void* hip_stream);
+/* The inverse (Alg. 4, last step): out_rgb (dev) = rgb, except every pixel
+ * x of mask, which takes aligned (dev, the inpainted aligned video) sampled
+ * at M_n(x), clamped to the frame, by bilinear interpolation.  Syncs.
+ * Errors: VI_E_INVAL, VI_E_HIP. */
+vi_status vi_align_unwarp(const uint8_t* aligned, const uint8_t* rgb, const uint8_t* mask,
+                          int32_t W, int32_t H, int32_t T, const double* M, uint8_t* out_rgb,
+                          void* hip_stream);
+
 /* Work counters of a context since creation or the last reset (host out).
  * effective_evals is read back from the device: syncs. */
 typedef struct {

@@ -275,7 +275,7 @@ int vio_align_compose(const double* theta, int32_t T, double* M) {
 static int sample_rgb(const uint8_t* fr, const uint8_t* occ, int W, int H, double xs, double ys,
                       uint8_t out[3]) {
   const double fl_x = floor(xs), fl_y = floor(ys);
-  if (fl_x < 0.0 || fl_y < 0.0 || fl_x > W - 1.0 || fl_y > H - 1.0) return 0;
+  if (!(fl_x >= 0.0 && fl_y >= 0.0 && fl_x <= W - 1.0 && fl_y <= H - 1.0)) return 0;
   const int x0 = (int)fl_x, y0 = (int)fl_y;
   const double fx = xs - fl_x, fy = ys - fl_y;
   const double w[4] = {(1.0 - fx) * (1.0 - fy), fx * (1.0 - fy), (1.0 - fx) * fy, fx * fy};

@@ -853,6 +853,86 @@ vi_status vi_onion_layer_noalloc(vi_ctx* c, uint8_t* Hp, int32_t layer, float* o
   return sync(c);
 }
 
+vi_status vi_align_params_default(vi_align_params* o) {
+  if (!o) return fail(VI_E_INVAL, "null params");
+  o->levels = 3;
+  o->iters = 8;
+  o->tukey_c = 20.0;
+  return VI_OK;
+}
+
+vi_status vi_align_estimate(const uint8_t* rgb, const uint8_t* mask, int32_t W, int32_t H,
+                            int32_t T, const vi_align_params* prm, double* theta,
+                            void* hip_stream) {
+  if (!rgb || !mask || !prm || !theta) return fail(VI_E_INVAL, "null argument");
+  if (T < 2) return fail(VI_E_INVAL, "the motion estimation needs at least two frames");
+  if (prm->levels < 1 || prm->levels > 8 || prm->iters < 0 || prm->iters > 100 ||
+      !(prm->tukey_c > 0.0))
+    return fail(VI_E_INVAL, "levels in [1, 8], iters in [0, 100], tukey_c > 0");
+  if (W < 8 || H < 8 || W >= 32768 || H >= 32768 || (int64_t)W * H * T >= (int64_t(1) << 31))
+    return fail(VI_E_INVAL, "W, H in [8, 32768) and W*H*T < 2^31");
+  int32_t w = W, h = H;
+  for (int l = 1; l < prm->levels; ++l) {
+    w = (w + 1) / 2;
+    h = (h + 1) / 2;
+  }
+  if (w < 8 || h < 8) return fail(VI_E_INVAL, "the coarsest estimation level is below 8x8");
+  std::string err;
+  const vi_status st = vi::align_estimate(rgb, mask, W, H, T, prm, theta,
+                                          static_cast<hipStream_t>(hip_stream), &err);
+  return st == VI_OK ? VI_OK : fail(st, "vi_align_estimate: " + err);
+}
+
+vi_status vi_align_compose(const double* theta, int32_t T, double* M) {
+  if (!M || T < 1 || (T > 1 && !theta)) return fail(VI_E_INVAL, "null argument or T < 1");
+  if (vi::align_compose(theta, T, M) != VI_OK) return fail(VI_E_INVAL, "a singular frame map");
+  return VI_OK;
+}
+
+namespace {
+// device space for 6 T doubles, from the block pool of the current device
+struct MapBuf {
+  int dev = 0;
+  double* p = nullptr;
+  vi_status get(int32_t T) {
+    if (hipGetDevice(&dev) != hipSuccess) return fail(VI_E_HIP, "no current device");
+    p = static_cast<double*>(vi::pool_alloc(dev, sizeof(double) * 6 * (size_t)T));
+    return p ? VI_OK : fail(VI_E_NOMEM, "device allocation failed");
+  }
+  ~MapBuf() {
+    if (p) vi::pool_free(dev, p);
+  }
+};
+}  // namespace
+
+vi_status vi_align_warp(const uint8_t* rgb, const uint8_t* mask, int32_t W, int32_t H,
+                        int32_t T, const double* M, uint8_t* out_rgb, uint8_t* out_mask,
+                        void* hip_stream) {
+  if (!rgb || !mask || !M || !out_rgb || !out_mask) return fail(VI_E_INVAL, "null argument");
+  if (W < 1 || H < 1 || T < 1 || W >= 32768 || H >= 32768 ||
+      (int64_t)W * H * T >= (int64_t(1) << 31))
+    return fail(VI_E_INVAL, "W, H, T >= 1 and W*H*T < 2^31");
+  MapBuf buf;
+  VI_TRY(buf.get(T));
+  const vi_status st = vi::align_warp(rgb, mask, W, H, T, M, buf.p, out_rgb, out_mask,
+                                      static_cast<hipStream_t>(hip_stream));
+  return st == VI_OK ? VI_OK : fail(st, "vi_align_warp failed (singular map or HIP error)");
+}
+
+vi_status vi_align_unwarp(const uint8_t* aligned, const uint8_t* rgb, const uint8_t* mask,
+                          int32_t W, int32_t H, int32_t T, const double* M, uint8_t* out_rgb,
+                          void* hip_stream) {
+  if (!aligned || !rgb || !mask || !M || !out_rgb) return fail(VI_E_INVAL, "null argument");
+  if (W < 1 || H < 1 || T < 1 || W >= 32768 || H >= 32768 ||
+      (int64_t)W * H * T >= (int64_t(1) << 31))
+    return fail(VI_E_INVAL, "W, H, T >= 1 and W*H*T < 2^31");
+  MapBuf buf;
+  VI_TRY(buf.get(T));
+  const vi_status st = vi::align_unwarp(aligned, rgb, mask, W, H, T, M, buf.p, out_rgb,
+                                        static_cast<hipStream_t>(hip_stream));
+  return st == VI_OK ? VI_OK : fail(st, "vi_align_unwarp failed (HIP error)");
+}
+
 vi_status vi_transition(vi_ctx* c, int32_t level) {
   VI_TRY(level_ok(c, level));
   if (level + 1 >= c->L) return fail(VI_E_INVAL, "no coarser level");

@@ -27,6 +27,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
+#include "vi.h"
+
 namespace vi {
 
 // Division by a run-time invariant divisor (Granlund & Montgomery, "Division
@@ -203,6 +207,20 @@ void pool_free(int dev, void* p);
 size_t pool_trim(int dev);
 hipEvent_t event_get(int dev);
 void event_put(int dev, hipEvent_t e);
+
+// Realignment (vi_align.hip): the C ABI's checks are done by the caller;
+// err receives a message on failure.  d_minv / d_m: device space for 6 T
+// doubles.
+vi_status align_estimate(const uint8_t* rgb, const uint8_t* mask, int32_t W, int32_t H, int32_t T,
+                         const vi_align_params* prm, double* theta, hipStream_t st,
+                         std::string* err);
+vi_status align_compose(const double* theta, int32_t T, double* M);
+vi_status align_warp(const uint8_t* rgb, const uint8_t* mask, int32_t W, int32_t H, int32_t T,
+                     const double* M, double* d_minv, uint8_t* out_rgb, uint8_t* out_mask,
+                     hipStream_t st);
+vi_status align_unwarp(const uint8_t* aligned, const uint8_t* rgb, const uint8_t* mask, int32_t W,
+                       int32_t H, int32_t T, const double* M, double* d_m, uint8_t* out,
+                       hipStream_t st);
 
 // stream compaction (stable): out[k] = i for the k-th i with flags[i] != 0
 size_t compact_temp_bytes(int32_t n);

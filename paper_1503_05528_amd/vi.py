@@ -47,7 +47,19 @@ class ViError(RuntimeError):
 
 # exported symbols and their (restype, argtypes)
 _vp, _i32, _i64, _u64, _f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+class AlignParams(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("iters", C.c_int32), ("tukey_c", C.c_double)]
+
+
+_f64p = C.POINTER(C.c_double)
+
 SIGNATURES = {
+    "vi_align_params_default": (_i32, [C.POINTER(AlignParams)]),
+    "vi_align_estimate": (_i32, [_vp, _vp, _i32, _i32, _i32, C.POINTER(AlignParams), _f64p,
+                                 _vp]),
+    "vi_align_compose": (_i32, [_f64p, _i32, _f64p]),
+    "vi_align_warp": (_i32, [_vp, _vp, _i32, _i32, _i32, _f64p, _vp, _vp, _vp]),
+    "vi_align_unwarp": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _f64p, _vp, _vp]),
     "vi_params_default": (_i32, [C.c_void_p]),
     "vi_create": (_i32, [C.POINTER(_vp), C.c_void_p, _i32, _i32, _i32, _vp, _vp, _vp]),
     "vi_level_info": (_i32, [_vp, _i32, C.POINTER(_i32), C.POINTER(_i64)]),
@@ -402,3 +414,85 @@ class Batch:
             if self.step() == len(self.members):
                 return k + 1
         raise RuntimeError("batch did not finish")
+
+
+
+# ---------------------------------------------------------------- realignment
+# (Sec. 3.4, Alg. 2, and the inverse warp of Alg. 4)
+
+def align_params(**kw) -> AlignParams:
+    p = AlignParams()
+    _check("vi_align_params_default", lib().vi_align_params_default(C.byref(p)))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _f64(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, np.float64)
+    return a, a.ctypes.data_as(_f64p)
+
+
+def align_estimate(video: torch.Tensor, mask: torch.Tensor, stream=None, **kw):
+    """theta [T-1][6] (numpy float64): the dominant affine motion of every
+    pair of successive frames; video [T][H][W][3] and mask [T][H][W] uint8 on
+    the GPU."""
+    import numpy as np
+    T, H, W, _ = video.shape
+    th = np.zeros((T - 1, 6), np.float64)
+    p = align_params(**kw)
+    torch.cuda.synchronize(video.device)
+    _check("vi_align_estimate", lib().vi_align_estimate(
+        _ptr(video), _ptr(mask), W, H, T, C.byref(p), th.ctypes.data_as(_f64p),
+        _stream_handle(stream)))
+    return th
+
+
+def align_compose(theta, T: int):
+    """M [T][6]: every frame's map to the reference (middle) frame."""
+    import numpy as np
+    th, thp = _f64(theta)
+    M = np.zeros((T, 6), np.float64)
+    _check("vi_align_compose", lib().vi_align_compose(thp, T, M.ctypes.data_as(_f64p)))
+    return M
+
+
+def align_warp(video: torch.Tensor, mask: torch.Tensor, M, stream=None):
+    """The aligned video and occlusion (device tensors)."""
+    T, H, W, _ = video.shape
+    out = torch.empty_like(video)
+    om = torch.empty_like(mask)
+    Mm, Mp = _f64(M)
+    torch.cuda.synchronize(video.device)
+    _check("vi_align_warp", lib().vi_align_warp(_ptr(video), _ptr(mask), W, H, T, Mp, _ptr(out),
+                                                _ptr(om), _stream_handle(stream)))
+    return out, om
+
+
+def align_unwarp(aligned: torch.Tensor, video: torch.Tensor, mask: torch.Tensor, M,
+                 stream=None):
+    """The input video with its occluded pixels taken from the aligned
+    (inpainted) video at their reference positions (device tensor)."""
+    T, H, W, _ = video.shape
+    out = torch.empty_like(video)
+    Mm, Mp = _f64(M)
+    torch.cuda.synchronize(video.device)
+    _check("vi_align_unwarp", lib().vi_align_unwarp(_ptr(aligned), _ptr(video), _ptr(mask), W,
+                                                    H, T, Mp, _ptr(out),
+                                                    _stream_handle(stream)))
+    return out
+
+
+def inpaint_realigned(video: torch.Tensor, mask: torch.Tensor, align=None, **kw):
+    """Alg. 4 with its realignment: estimate, compose, warp, inpaint the
+    aligned video, unwarp into the original occlusion.  Returns (output,
+    theta, M)."""
+    T = video.shape[0]
+    theta = align_estimate(video, mask, **(align or {}))
+    M = align_compose(theta, T)
+    av, am = align_warp(video, mask, M)
+    g = Clip(av, am, **kw)
+    inp = g.inpaint()
+    g.close()
+    return align_unwarp(inp, video, mask, M), theta, M
