@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="hd", choices=["sd", "hd", "tiny"])
+    ap.add_argument("--no-realign", action="store_true",
+                    help="skip the realignment measurement (Sec. 3.4)")
     ap.add_argument("--no-sd", action="store_true",
                     help="skip the SD clip measured beside the headline workload")
     ap.add_argument("--sd-steps", type=int, default=3)
@@ -436,6 +438,67 @@ def served_sweep(rates, n_jobs, em_iters):
             "mean_serial_service_s": mean_svc}
 
 
+def measure_realign(steps=3):
+    """Realignment of a shaking-camera clip (854x480 px x 50 frames):
+    estimation of every frame pair's motion, composition, warp of video and
+    occlusion, unwarp into the occlusion; GPU times (inputs resident in HBM)
+    and the oracle's estimation and warp on the host."""
+    import numpy as np
+    import torch
+    from paper_1503_05528_amd import synth, vi
+    clip, cams = synth.jittered(seed=11, W=854, H=480, T=50)
+    T, H, W, _ = clip.video.shape
+    v = torch.from_numpy(clip.occluded_input()).cuda()
+    m = torch.from_numpy(clip.mask).cuda()
+    aligned = torch.from_numpy(clip.video).cuda()
+    theta = vi.align_estimate(v, m)  # warm-up
+    M = vi.align_compose(theta, T)
+    vi.align_warp(v, m, M)
+    torch.cuda.synchronize()
+    t_est, t_warp, t_unwarp = [], [], []
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        theta = vi.align_estimate(v, m)
+        M = vi.align_compose(theta, T)
+        s1 = time.perf_counter()
+        av, am = vi.align_warp(v, m, M)
+        torch.cuda.synchronize()
+        s2 = time.perf_counter()
+        out = vi.align_unwarp(aligned, v, m, M)
+        torch.cuda.synchronize()
+        s3 = time.perf_counter()
+        t_est.append(s1 - s0)
+        t_warp.append(s2 - s1)
+        t_unwarp.append(s3 - s2)
+    est, warp, unwarp = (statistics.median(x) for x in (t_est, t_warp, t_unwarp))
+    # truth: the cameras' exact inter-frame motion, corner error in px
+    def h3(q):
+        return np.array([[q[0], q[1], q[2]], [q[3], q[4], q[5]], [0, 0, 1.0]])
+    cn = np.array([[0, 0, 1], [W - 1, 0, 1], [0, H - 1, 1], [W - 1, H - 1, 1.0]]).T
+    err = max(np.abs(((np.linalg.inv(h3(cams[n + 1])) @ h3(cams[n])) @ cn - h3(theta[n]) @ cn)[:2]).max()
+              for n in range(T - 1))
+    px = W * H * T
+    # warp: per output pixel the source frame's 3 colour bytes and mask byte
+    # (the 2x2 stencil overlaps its neighbours') and 4 bytes written
+    warp_bytes = 8 * px
+    from oracle import vio
+    vn, mn = clip.occluded_input(), clip.mask
+    c0 = time.perf_counter()
+    oth = vio.align_estimate(vn, mn)
+    c1 = time.perf_counter()
+    vio.align_warp(vn, mn, vio.align_compose(oth, T))
+    c2 = time.perf_counter()
+    return {"workload": f"shaking-camera clip {W}x{H}x{T}, 3 estimation levels x 8 robust "
+                        "Gauss-Newton steps per frame pair",
+            "estimate_ms": 1000 * est, "warp_ms": 1000 * warp, "unwarp_ms": 1000 * unwarp,
+            "frames_per_s": T / (est + warp + unwarp),
+            "max_corner_error_px": float(err),
+            "warp_call_gbs": warp_bytes / warp / 1e9,
+            "warp_call_frac_of_hbm_peak": warp_bytes / warp / 1e9 / HBM_PEAK_GBS,
+            "oracle_estimate_s": c1 - c0, "oracle_warp_s": c2 - c1,
+            "oracle_threads": vio.num_threads()}
+
+
 def make_clip(name):
     from paper_1503_05528_amd import synth
     if name == "sd":
@@ -793,6 +856,9 @@ def main():
         s.pop("clip")
         line["sd_temporal"] = {k: s[k] for k in ("workload", "value", "ms_per_step",
                                                  "clips_per_s", "kernel_ms_per_step")}
+    if not a.no_realign:
+        log("realignment: shaking-camera clip")
+        line["realign"] = measure_realign()
     if not a.no_batched or not a.no_served:
         bclips = gen_batch_clips(a.batch_clips)
         bres, service = batched_vs_serial(bclips, a.em_iters)

@@ -6,9 +6,10 @@
 // residual r(x) = g_{n+1}(x + w(x)) - g_n(x) (grey g = (R+G+B)/3, Tukey
 // biweight, w affine in the coordinates relative to the frame centre).  All
 // pairs advance together: one kernel evaluates every pixel of every pair and
-// writes per-workgroup partial sums of the 6x6 normal equations, a second
-// sums them per pair in a fixed order, and the host solves the 6x6 systems
-// (double precision throughout).  The warp and its inverse are pixel-parallel
+// writes per-workgroup partial sums of the 6x6 normal equations, and one
+// workgroup per pair sums them in a fixed order, solves the 6x6 system and
+// updates the pair's parameters; every step of every level is enqueued at
+// once (double precision throughout).  The warp and its inverse are pixel-parallel
 // bilinear resampling kernels in double precision with the products and sums
 // rounded one by one (no fused multiply-add), so that they reproduce the same
 // arithmetic sequence wherever the same map is applied.
@@ -41,10 +42,13 @@ struct GLevel {
   uint8_t* occ; // OR-pooled occlusion
 };
 
+// Pixel kernels run on (x blocks, y, t) grids: no integer division per
+// pixel.
 __global__ void k_grey0(const uint8_t* __restrict__ rgb, const uint8_t* __restrict__ mask,
-                        int64_t n, double* __restrict__ g, uint8_t* __restrict__ occ) {
-  const int64_t i = (int64_t)blockIdx.x * kAB + threadIdx.x;
-  if (i >= n) return;
+                        int32_t W, int32_t H, double* __restrict__ g, uint8_t* __restrict__ occ) {
+  const int32_t x = blockIdx.x * kAB + threadIdx.x;
+  if (x >= W) return;
+  const int64_t i = ((int64_t)blockIdx.z * H + blockIdx.y) * W + x;
   const uint8_t o = mask[i] ? 1 : 0;
   occ[i] = o;
   const double s = __dadd_rn(__dadd_rn((double)rgb[3 * i], (double)rgb[3 * i + 1]),
@@ -52,13 +56,12 @@ __global__ void k_grey0(const uint8_t* __restrict__ rgb, const uint8_t* __restri
   g[i] = o ? 0.0 : s / 3.0;
 }
 
-__global__ void k_grey_down(GLevel F, GLevel C, int32_t T) {
-  const int64_t i = (int64_t)blockIdx.x * kAB + threadIdx.x;
-  const int64_t n = (int64_t)C.W * C.H * T;
-  if (i >= n) return;
-  const int32_t x = (int32_t)(i % C.W);
-  const int32_t y = (int32_t)((i / C.W) % C.H);
-  const int64_t t = i / ((int64_t)C.W * C.H);
+__global__ void k_grey_down(GLevel F, GLevel C) {
+  const int32_t x = blockIdx.x * kAB + threadIdx.x;
+  if (x >= C.W) return;
+  const int32_t y = blockIdx.y;
+  const int64_t t = blockIdx.z;
+  const int64_t i = (t * C.H + y) * C.W + x;
   double s = 0.0;
   int cnt = 0, any = 0;
   for (int by = 0; by < 2; ++by)
@@ -74,12 +77,11 @@ __global__ void k_grey_down(GLevel F, GLevel C, int32_t T) {
   C.g[i] = any ? 0.0 : s / (double)cnt;
 }
 
-__global__ void k_grey_grad(GLevel L, int32_t T) {
-  const int64_t i = (int64_t)blockIdx.x * kAB + threadIdx.x;
-  const int64_t n = (int64_t)L.W * L.H * T;
-  if (i >= n) return;
-  const int32_t x = (int32_t)(i % L.W);
-  const int32_t y = (int32_t)((i / L.W) % L.H);
+__global__ void k_grey_grad(GLevel L) {
+  const int32_t x = blockIdx.x * kAB + threadIdx.x;
+  if (x >= L.W) return;
+  const int32_t y = blockIdx.y;
+  const int64_t i = ((int64_t)blockIdx.z * L.H + y) * L.W + x;
   double gx = 0.0, gy = 0.0;
   if (x >= 1 && x < L.W - 1 && y >= 1 && y < L.H - 1) {
     gx = __dsub_rn(L.g[i + 1], L.g[i - 1]) / 2.0;
@@ -105,19 +107,19 @@ __global__ __launch_bounds__(kAB) void k_gn_partial(GLevel L, const double* __re
                                                     double c, int32_t nblk,
                                                     double* __restrict__ out) {
   const int32_t n = blockIdx.y;
-  const int64_t fr = (int64_t)L.W * L.H;
+  const int32_t fr = L.W * L.H;
   const double* p = P + 6 * n;
   const double cx = (L.W - 1) / 2.0, cy = (L.H - 1) / 2.0;
   double acc[kSums];
 #pragma unroll
   for (int k = 0; k < kSums; ++k) acc[k] = 0.0;
-  const int64_t base = (int64_t)blockIdx.x * kAB * kPixPerThread;
+  const int32_t base = blockIdx.x * kAB * kPixPerThread;
   for (int r = 0; r < kPixPerThread; ++r) {
-    const int64_t i = base + (int64_t)r * kAB + threadIdx.x;
+    const int32_t i = base + r * kAB + (int32_t)threadIdx.x;
     if (i >= fr) break;
-    const int64_t ia = n * fr + i;
+    const int64_t ia = (int64_t)n * fr + i;
     if (L.occ[ia]) continue;
-    const int32_t x = (int32_t)(i % L.W), y = (int32_t)(i / L.W);
+    const int32_t y = i / L.W, x = i - y * L.W;
     const double X = x - cx, Y = y - cy;
     const double u = p[0] + p[2] * X + p[3] * Y;
     const double v = p[1] + p[4] * X + p[5] * Y;
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(kAB) void k_gn_partial(GLevel L, const double* __re
     if (!(xs >= 1.0 && xs < L.W - 2.0 && ys >= 1.0 && ys < L.H - 2.0)) continue;
     const int32_t x0 = (int32_t)floor(xs), y0 = (int32_t)floor(ys);
     const double fx = xs - x0, fy = ys - y0;
-    const int64_t j = (n + 1) * fr + (int64_t)y0 * L.W + x0;
+    const int64_t j = (int64_t)(n + 1) * fr + (int64_t)y0 * L.W + x0;
     if (L.occ[j] | L.occ[j + 1] | L.occ[j + L.W] | L.occ[j + L.W + 1]) continue;
     const double I2 = bilin(L.g, L.W, j, fx, fy);
     const double Gx = bilin(L.gx, L.W, j, fx, fy);
@@ -161,20 +163,9 @@ __global__ __launch_bounds__(kAB) void k_gn_partial(GLevel L, const double* __re
   }
 }
 
-// per pair: the sum of its workgroups' partial sums, in workgroup order
-__global__ void k_gn_sum(const double* __restrict__ part, int32_t nblk, int32_t npairs,
-                         double* __restrict__ sums) {
-  const int32_t i = blockIdx.x * kAB + threadIdx.x;
-  if (i >= npairs * kSums) return;
-  const int32_t n = i / kSums, k = i % kSums;
-  double v = 0.0;
-  for (int32_t b = 0; b < nblk; ++b) v += part[((int64_t)n * nblk + b) * kSums + k];
-  sums[i] = v;
-}
-
 // Gaussian elimination with partial pivoting of the 6x6 system A d = b;
 // false if singular
-bool solve6(double A[6][6], const double b[6], double d[6]) {
+__device__ bool solve6(double A[6][6], const double b[6], double d[6]) {
   double M[6][7];
   for (int i = 0; i < 6; ++i) {
     for (int j = 0; j < 6; ++j) M[i][j] = A[i][j];
@@ -183,10 +174,14 @@ bool solve6(double A[6][6], const double b[6], double d[6]) {
   for (int c = 0; c < 6; ++c) {
     int piv = c;
     for (int r = c + 1; r < 6; ++r)
-      if (std::fabs(M[r][c]) > std::fabs(M[piv][c])) piv = r;
-    if (std::fabs(M[piv][c]) < 1e-9) return false;
+      if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
+    if (fabs(M[piv][c]) < 1e-9) return false;
     if (piv != c)
-      for (int j = 0; j < 7; ++j) std::swap(M[c][j], M[piv][j]);
+      for (int j = 0; j < 7; ++j) {
+        const double t = M[c][j];
+        M[c][j] = M[piv][j];
+        M[piv][j] = t;
+      }
     for (int r = c + 1; r < 6; ++r) {
       const double f = M[r][c] / M[c][c];
       for (int j = c; j < 7; ++j) M[r][j] -= f * M[c][j];
@@ -198,6 +193,39 @@ bool solve6(double A[6][6], const double b[6], double d[6]) {
     d[r] = s / M[r][r];
   }
   return true;
+}
+
+// One workgroup per pair: the pair's workgroup partial sums added in
+// workgroup order, the 6x6 system solved and the increment added to the
+// pair's parameters; `scale` doubles the translations afterwards (the step
+// to the next finer level).
+__global__ __launch_bounds__(64) void k_gn_solve(const double* __restrict__ part, int32_t nblk,
+                                                 double* __restrict__ P, int32_t scale) {
+  const int32_t n = blockIdx.x;
+  __shared__ double s[kSums];
+  if (threadIdx.x < kSums) {
+    double v = 0.0;
+    for (int32_t b = 0; b < nblk; ++b) v += part[((int64_t)n * nblk + b) * kSums + threadIdx.x];
+    s[threadIdx.x] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double A[6][6], rhs[6], d[6];
+  int q = 0;
+  for (int a = 0; a < 6; ++a)
+    for (int c2 = a; c2 < 6; ++c2) {
+      A[a][c2] = s[q];
+      A[c2][a] = s[q];
+      ++q;
+    }
+  for (int a = 0; a < 6; ++a) rhs[a] = -s[21 + a];
+  double* p = P + 6 * n;
+  if (solve6(A, rhs, d))
+    for (int a = 0; a < 6; ++a) p[a] += d[a];
+  if (scale) {
+    p[0] *= 2.0;
+    p[1] *= 2.0;
+  }
 }
 
 // The bilinear sample of an RGB frame at (xs, ys): neighbours of nonzero
@@ -243,10 +271,11 @@ __global__ void k_warp(const uint8_t* __restrict__ rgb, const uint8_t* __restric
                        int32_t W, int32_t H, int32_t T, const double* __restrict__ Minv,
                        uint8_t* __restrict__ out_rgb, uint8_t* __restrict__ out_mask) {
   const int64_t fr = (int64_t)W * H;
-  const int64_t i = (int64_t)blockIdx.x * kAB + threadIdx.x;
-  if (i >= fr * T) return;
-  const int64_t t = i / fr;
-  const int32_t x = (int32_t)(i % W), y = (int32_t)((i / W) % H);
+  const int32_t x = blockIdx.x * kAB + threadIdx.x;
+  if (x >= W) return;
+  const int32_t y = blockIdx.y;
+  const int64_t t = blockIdx.z;
+  const int64_t i = t * fr + (int64_t)y * W + x;
   double xs, ys;
   apply(Minv + 6 * t, x, y, xs, ys);
   uint32_t v[3] = {0, 0, 0};
@@ -261,16 +290,17 @@ __global__ void k_unwarp(const uint8_t* __restrict__ aligned, const uint8_t* __r
                          const uint8_t* __restrict__ mask, int32_t W, int32_t H, int32_t T,
                          const double* __restrict__ M, uint8_t* __restrict__ out) {
   const int64_t fr = (int64_t)W * H;
-  const int64_t i = (int64_t)blockIdx.x * kAB + threadIdx.x;
-  if (i >= fr * T) return;
+  const int32_t x = blockIdx.x * kAB + threadIdx.x;
+  if (x >= W) return;
+  const int32_t y = blockIdx.y;
+  const int64_t t = blockIdx.z;
+  const int64_t i = t * fr + (int64_t)y * W + x;
   if (!mask[i]) {
     out[3 * i] = rgb[3 * i];
     out[3 * i + 1] = rgb[3 * i + 1];
     out[3 * i + 2] = rgb[3 * i + 2];
     return;
   }
-  const int64_t t = i / fr;
-  const int32_t x = (int32_t)(i % W), y = (int32_t)((i / W) % H);
   double xs, ys;
   apply(M + 6 * t, x, y, xs, ys);
   xs = xs < 0.0 ? 0.0 : (xs > W - 1.0 ? W - 1.0 : xs);
@@ -282,7 +312,10 @@ __global__ void k_unwarp(const uint8_t* __restrict__ aligned, const uint8_t* __r
   out[3 * i + 2] = (uint8_t)v[2];
 }
 
-inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + kAB - 1) / kAB)); }
+// x blocks of kAB pixels, one row per y, one frame per z
+inline dim3 grid3(int32_t W, int32_t H, int32_t T) {
+  return dim3((unsigned)((W + kAB - 1) / kAB), (unsigned)H, (unsigned)T);
+}
 
 // the inverse of an affine map; false if singular
 bool inverse(const double* m, double* inv) {
@@ -344,72 +377,50 @@ vi_status align_estimate(const uint8_t* rgb, const uint8_t* mask, int32_t W, int
     w = (w + 1) / 2;
     h = (h + 1) / 2;
   }
-  k_grey0<<<grid1(fr0 * T), kAB, 0, st>>>(rgb, mask, fr0 * T, lv[0].g, lv[0].occ);
+  k_grey0<<<grid3(W, H, T), kAB, 0, st>>>(rgb, mask, W, H, lv[0].g, lv[0].occ);
   for (int l = 1; l < Lm; ++l)
-    k_grey_down<<<grid1((int64_t)lv[(size_t)l].W * lv[(size_t)l].H * T), kAB, 0, st>>>(
-        lv[(size_t)l - 1], lv[(size_t)l], T);
+    k_grey_down<<<grid3(lv[(size_t)l].W, lv[(size_t)l].H, T), kAB, 0, st>>>(
+        lv[(size_t)l - 1], lv[(size_t)l]);
   for (int l = 0; l < Lm; ++l)
-    k_grey_grad<<<grid1((int64_t)lv[(size_t)l].W * lv[(size_t)l].H * T), kAB, 0, st>>>(
-        lv[(size_t)l], T);
+    k_grey_grad<<<grid3(lv[(size_t)l].W, lv[(size_t)l].H, T), kAB, 0, st>>>(lv[(size_t)l]);
   const int32_t np = T - 1;
   const int64_t per_blk = (int64_t)kAB * kPixPerThread;
   const int32_t nblk_max = (int32_t)((fr0 + per_blk - 1) / per_blk);
-  double *d_p = nullptr, *d_part = nullptr, *d_sums = nullptr;
+  double *d_p = nullptr, *d_part = nullptr;
   if (!dmalloc((void**)&d_p, sizeof(double) * 6 * (size_t)np) ||
-      !dmalloc((void**)&d_part, sizeof(double) * kSums * (size_t)np * (size_t)nblk_max) ||
-      !dmalloc((void**)&d_sums, sizeof(double) * kSums * (size_t)np)) {
+      !dmalloc((void**)&d_part, sizeof(double) * kSums * (size_t)np * (size_t)nblk_max)) {
     cleanup();
     *err = "device allocation failed";
     return VI_E_NOMEM;
   }
-  if (hipGetLastError() != hipSuccess) {
+  std::vector<double> p((size_t)6 * np, 0.0);
+  if (hipMemcpyAsync(d_p, p.data(), sizeof(double) * p.size(), hipMemcpyHostToDevice, st) !=
+      hipSuccess) {
     cleanup();
-    *err = "pyramid launch failed";
+    *err = "parameter upload failed";
     return VI_E_HIP;
   }
-  std::vector<double> p((size_t)6 * np, 0.0), sums((size_t)kSums * np);
+  // every step of every level is enqueued at once: the partial sums, then
+  // one workgroup per pair that solves and updates the pair's parameters
   for (int l = Lm - 1; l >= 0; --l) {
     const GLevel& L = lv[(size_t)l];
     const int64_t fr = (int64_t)L.W * L.H;
     const int32_t nblk = (int32_t)((fr + per_blk - 1) / per_blk);
     for (int k = 0; k < prm->iters; ++k) {
-      if (hipMemcpyAsync(d_p, p.data(), sizeof(double) * p.size(), hipMemcpyHostToDevice, st) !=
-          hipSuccess) {
-        cleanup();
-        *err = "parameter upload failed";
-        return VI_E_HIP;
-      }
       k_gn_partial<<<dim3((unsigned)nblk, (unsigned)np), kAB, 0, st>>>(L, d_p, prm->tukey_c,
                                                                         nblk, d_part);
-      k_gn_sum<<<grid1((int64_t)np * kSums), kAB, 0, st>>>(d_part, nblk, np, d_sums);
-      if (hipGetLastError() != hipSuccess ||
-          hipMemcpyAsync(sums.data(), d_sums, sizeof(double) * sums.size(),
-                         hipMemcpyDeviceToHost, st) != hipSuccess ||
-          hipStreamSynchronize(st) != hipSuccess) {
-        cleanup();
-        *err = "Gauss-Newton step failed";
-        return VI_E_HIP;
-      }
-      for (int32_t n = 0; n < np; ++n) {
-        const double* s = sums.data() + (size_t)kSums * n;
-        double A[6][6], b[6], d[6];
-        int q = 0;
-        for (int a = 0; a < 6; ++a)
-          for (int c2 = a; c2 < 6; ++c2) {
-            A[a][c2] = s[q];
-            A[c2][a] = s[q];
-            ++q;
-          }
-        for (int a = 0; a < 6; ++a) b[a] = -s[21 + a];
-        if (!solve6(A, b, d)) continue;
-        for (int a = 0; a < 6; ++a) p[(size_t)6 * n + a] += d[a];
-      }
+      const int32_t scale = (l > 0 && k == prm->iters - 1) ? 1 : 0;
+      k_gn_solve<<<dim3((unsigned)np), 64, 0, st>>>(d_part, nblk, d_p, scale);
     }
-    if (l > 0)
-      for (int32_t n = 0; n < np; ++n) {
-        p[(size_t)6 * n] *= 2.0;
-        p[(size_t)6 * n + 1] *= 2.0;
-      }
+    if (l > 0 && prm->iters == 0) k_gn_solve<<<dim3((unsigned)np), 64, 0, st>>>(d_part, 0, d_p, 1);
+  }
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(p.data(), d_p, sizeof(double) * p.size(), hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    cleanup();
+    *err = "Gauss-Newton steps failed";
+    return VI_E_HIP;
   }
   cleanup();
   const double cx = (W - 1) / 2.0, cy = (H - 1) / 2.0;
@@ -449,8 +460,7 @@ vi_status align_warp(const uint8_t* rgb, const uint8_t* mask, int32_t W, int32_t
   if (hipMemcpyAsync(d_minv, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice,
                      st) != hipSuccess)
     return VI_E_HIP;
-  k_warp<<<grid1((int64_t)W * H * T), kAB, 0, st>>>(rgb, mask, W, H, T, d_minv, out_rgb,
-                                                    out_mask);
+  k_warp<<<grid3(W, H, T), kAB, 0, st>>>(rgb, mask, W, H, T, d_minv, out_rgb, out_mask);
   if (hipGetLastError() != hipSuccess) return VI_E_HIP;
   // the host copy of the inverses must outlive the transfer
   return hipStreamSynchronize(st) == hipSuccess ? VI_OK : VI_E_HIP;
@@ -462,7 +472,7 @@ vi_status align_unwarp(const uint8_t* aligned, const uint8_t* rgb, const uint8_t
   if (hipMemcpyAsync(d_m, M, sizeof(double) * 6 * (size_t)T, hipMemcpyHostToDevice, st) !=
       hipSuccess)
     return VI_E_HIP;
-  k_unwarp<<<grid1((int64_t)W * H * T), kAB, 0, st>>>(aligned, rgb, mask, W, H, T, d_m, out);
+  k_unwarp<<<grid3(W, H, T), kAB, 0, st>>>(aligned, rgb, mask, W, H, T, d_m, out);
   if (hipGetLastError() != hipSuccess) return VI_E_HIP;
   return hipStreamSynchronize(st) == hipSuccess ? VI_OK : VI_E_HIP;
 }
