@@ -25,8 +25,8 @@
  *   - Colour and texture channels are integers 0..255; a voxel carries five
  *     channels R, G, B, Tx, Ty.
  *   - Limits: W < 32768, H < 32768, T < 32768, W*H*T < 2^31, levels <= 8,
- *     patch = 5x5x5, 1 <= jump-flood step <= 4, lambda <= 130 (keeps the
- *     integer distance below 2^31).
+ *     patch = 5x5x5 (or 5x5x1 with T = 1), 1 <= jump-flood step <= 4,
+ *     lambda <= 130 (keeps the integer distance below 2^31).
  */
 #ifndef VI_H
 #define VI_H
@@ -52,7 +52,9 @@ typedef enum { VI_RECON_WEIGHTED = 0, VI_RECON_MEAN = 1, VI_RECON_BEST = 2 } vi_
 /* Method parameters; vi_params_default() fills the paper's values (Sec. 3.7). */
 typedef struct {
   int32_t abi_version;  /* 1 */
-  int32_t patch[3];     /* (x, y, t) patch size; only {5, 5, 5} (Sec. 3.7) */
+  int32_t patch[3];     /* (x, y, t) patch size: {5, 5, 5} for videos (Sec. 3.7),
+                           or {5, 5, 1} for a single image (T = 1): 2-D image
+                           inpainting with the same method (Sec. 3.1, 3.5) */
   int32_t levels;       /* pyramid levels L >= 1 (Sec. 3.6) */
   int32_t lambda;       /* texture weight in the distance, 50 (Sec. 3.3, 3.7) */
   int32_t pm_iters;     /* PatchMatch iterations K, 10 (Sec. 3.1, 3.7) */

@@ -167,8 +167,10 @@ int64_t per_target_evals(const vi_params& p, int32_t rmax);
 vi_status check_params(const vi_params* p) {
   if (!p) return fail(VI_E_INVAL, "null params");
   if (p->abi_version != 1) return fail(VI_E_INVAL, "abi_version must be 1");
-  if (p->patch[0] != 5 || p->patch[1] != 5 || p->patch[2] != 5)
-    return fail(VI_E_INVAL, "only 5x5x5 patches are supported");
+  if (p->patch[0] != 5 || p->patch[1] != 5 || (p->patch[2] != 5 && p->patch[2] != 1))
+    return fail(VI_E_INVAL, "patches are 5x5x5 (videos) or 5x5x1 (single images)");
+  if (p->patch[2] == 1 && p->temporal_subsample)
+    return fail(VI_E_INVAL, "5x5x1 patches are for single images: no temporal subsampling");
   if (p->levels < 1 || p->levels > kMaxLevels) return fail(VI_E_INVAL, "levels must be in [1, 8]");
   if (p->lambda < 0 || p->lambda > 130) return fail(VI_E_INVAL, "lambda must be in [0, 130]");
   if (p->pm_iters < 0 || p->pm_iters > 64) return fail(VI_E_INVAL, "pm_iters must be in [0, 64]");
@@ -189,8 +191,9 @@ vi_status check_params(const vi_params* p) {
 int32_t coarser_T(const vi_params* p, int32_t T) { return p->temporal_subsample ? (T + 1) / 2 : T; }
 
 vi_status check_dims(const vi_params* p, int32_t W, int32_t H, int32_t T) {
-  if (W < 5 || H < 5 || T < 5 || W >= 32768 || H >= 32768 || T >= 32768)
-    return fail(VI_E_INVAL, "W, H, T must be in [5, 32768)");
+  if (p->patch[2] == 1 && T != 1) return fail(VI_E_INVAL, "5x5x1 patches need T = 1 (one image)");
+  if (W < 5 || H < 5 || T < p->patch[2] || W >= 32768 || H >= 32768 || T >= 32768)
+    return fail(VI_E_INVAL, "W, H must be in [5, 32768), T in [patch depth, 32768)");
   if ((int64_t)W * H * T >= (int64_t(1) << 31)) return fail(VI_E_INVAL, "W*H*T must be < 2^31");
   int32_t w = W, h = H, t = T;
   for (int l = 1; l < p->levels; ++l) {
@@ -198,7 +201,8 @@ vi_status check_dims(const vi_params* p, int32_t W, int32_t H, int32_t T) {
     h = (h + 1) / 2;
     t = coarser_T(p, t);
   }
-  if (w < 5 || h < 5 || t < 5) return fail(VI_E_INVAL, "the coarsest level is smaller than a patch");
+  if (w < 5 || h < 5 || t < p->patch[2])
+    return fail(VI_E_INVAL, "the coarsest level is smaller than a patch");
   return VI_OK;
 }
 
@@ -649,6 +653,7 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
     d.fdWH = vi::make_fastdiv((uint32_t)(w * h));
     d.lambda = prm->lambda;
     d.seed = prm->seed;
+    d.ht = prm->patch[2] / 2;
     const size_t V = (size_t)d.V;
     if ((st = dalloc(c, &d.vox, V + 2 * vi::kVoxPad)) || (st = dalloc(c, &d.hole, V)) ||
         (st = dalloc(c, &d.dsrc, V)) || (st = dalloc(c, &d.htil, V)) ||

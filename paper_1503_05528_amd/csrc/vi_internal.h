@@ -69,6 +69,8 @@ struct DevLevel {
   uint16_t* chg;
   uint8_t* rmark;
   int32_t repoch;  // epoch of the next reconstruction of the level (from 1)
+  int32_t ht;      // temporal half-size of a patch: 2 (5x5x5 video patches) or 0
+                   // (5x5x1 patches of single images, T = 1)
   int32_t lambda;
   uint64_t seed;
 };

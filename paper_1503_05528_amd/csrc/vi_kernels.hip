@@ -86,6 +86,9 @@ __constant__ int8_t kRowDt[25] = {0, 0, 0, -1, 1, 0, 0, -1, -1, 1, 1, -2, 2,
                                   -1, -1, 1, 1, -2, -2, 2, 2, -2, -2, 2, 2};
 __constant__ int8_t kRowDy[25] = {0, -1, 1, 0, 0, -2, 2, -1, 1, -1, 1, 0, 0,
                                   -2, 2, -2, 2, -1, 1, -1, 1, -2, 2, -2, 2};
+// the five rows of a 5x5x1 patch (single images), centre out
+__constant__ int8_t kRowDt2[5] = {0, 0, 0, 0, 0};
+__constant__ int8_t kRowDy2[5] = {0, -1, 1, -2, 2};
 
 struct SsdAcc {
   uint32_t sc, st;  // colour and texture partial sums
@@ -195,24 +198,30 @@ __device__ __forceinline__ uint32_t ssd_groups(const DevLevel& L, const uint8_t*
                                                uint32_t abort_above, int32_t& nvox) {
   SsdAcc q{0u, 0u, 0};
   const uint32_t lam = (uint32_t)L.lambda;
+  // 25 rows (dt, dy) of a video patch, or the 5 rows of an image patch; the
+  // row counts after the centre (24, 4) are multiples of both group sizes
+  const bool vid = L.ht != 0;
+  const int nrows = vid ? 25 : 5;
+  const int8_t* rdt = vid ? kRowDt : kRowDt2;
+  const int8_t* rdy = vid ? kRowDy : kRowDy2;
   ssd_row<FULL, MASKED>(L, excl, p, px, py, pt, c, 0, 0, q);
   if (ABORT) {
 #pragma unroll 1
-    for (int r = 1; r < 25; r += 2) {
+    for (int r = 1; r < nrows; r += 2) {
       if (q.sc + lam * q.st > abort_above) break;
-      ssd_row<FULL, MASKED>(L, excl, p, px, py, pt, c, kRowDt[r], kRowDy[r], q);
-      ssd_row<FULL, MASKED>(L, excl, p, px, py, pt, c, kRowDt[r + 1], kRowDy[r + 1], q);
+      ssd_row<FULL, MASKED>(L, excl, p, px, py, pt, c, rdt[r], rdy[r], q);
+      ssd_row<FULL, MASKED>(L, excl, p, px, py, pt, c, rdt[r + 1], rdy[r + 1], q);
     }
   } else {
     // without early exit nothing orders the rows: four in flight at a time
 #pragma unroll 1
-    for (int r = 1; r < 25; r += 4) {
+    for (int r = 1; r < nrows; r += 4) {
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        ssd_row<FULL, MASKED>(L, excl, p, px, py, pt, c, kRowDt[r + j], kRowDy[r + j], q);
+        ssd_row<FULL, MASKED>(L, excl, p, px, py, pt, c, rdt[r + j], rdy[r + j], q);
     }
   }
-  nvox = FULL ? 125 : q.n;
+  nvox = FULL ? (vid ? 125 : 25) : q.n;
   return q.sc + lam * q.st;
 }
 
@@ -220,8 +229,8 @@ template <bool MASKED, bool ABORT>
 __device__ __forceinline__ uint32_t patch_ssd(const DevLevel& L, const uint8_t* __restrict__ excl,
                                               int32_t p, int32_t px, int32_t py, int32_t pt,
                                               int32_t c, uint32_t abort_above, int32_t& nvox) {
-  const bool interior = !MASKED && px >= 2 && py >= 2 && pt >= 2 && px < L.W - 2 &&
-                        py < L.H - 2 && pt < L.T - 2;
+  const bool interior = !MASKED && px >= 2 && py >= 2 && pt >= L.ht && px < L.W - 2 &&
+                        py < L.H - 2 && pt < L.T - L.ht;
   // wave-uniform choice: a whole wave of interior targets needs no masks
   if (__all(interior))
     return ssd_groups<true, MASKED, ABORT>(L, excl, p, px, py, pt, c, abort_above, nvox);
@@ -512,7 +521,7 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
       const int32_t R = A.R;
       const int32_t lox = max(2, cx - R), hix = min(L.W - 3, cx + R);
       const int32_t loy = max(2, cy - R), hiy = min(L.H - 3, cy + R);
-      const int32_t lot = max(2, ct - R), hit = min(L.T - 3, ct + R);
+      const int32_t lot = max(L.ht, ct - R), hit = min(L.T - 1 - L.ht, ct + R);
       uint64_t w[4];
       philox4x64_10((uint64_t)p, A.step, (uint64_t)A.rs_k, ((uint64_t)L.level << 8) | 0u, L.seed,
                     0, w);
@@ -1259,7 +1268,8 @@ __global__ void k_sources(DevLevel L) {
   if (i >= L.V) return;
   int32_t x, y, t;
   unlin(L, i, x, y, t);
-  const bool inner = x >= 2 && y >= 2 && t >= 2 && x < L.W - 2 && y < L.H - 2 && t < L.T - 2;
+  const bool inner =
+      x >= 2 && y >= 2 && t >= L.ht && x < L.W - 2 && y < L.H - 2 && t < L.T - L.ht;
   L.dsrc[i] = (uint8_t)(inner && !L.htil[i]);
 }
 

@@ -308,6 +308,14 @@ def jittered(seed: int = 4, W: int = 320, H: int = 240, T: int = 24, n_obj: int 
     return Clip(f"jitter{seed}", vid, mask, 2, seed), cams
 
 
+def image(seed: int, W: int, H: int, frac: float = 0.04, levels: int = 2, n_obj: int = 3,
+          kind: str = "ellipse", noise: float = 4.0) -> Clip:
+    """One still image (T = 1) from the same generator: grating background,
+    textured ellipses and a box or ellipse hole of about frac of the
+    pixels (2-D image inpainting with 5x5x1 patches)."""
+    return small(seed, W, H, 1, frac=frac, levels=levels, n_obj=n_obj, kind=kind, noise=noise)
+
+
 def served_trace(duration_s: float = 120.0, rate: float = 4.0, seed: int = 2000,
                  sd_frac: float = 0.10):
     """Poisson arrivals: list of (arrival_time_s, kind, seed) where kind is

@@ -367,3 +367,96 @@ def test_temporal_weighted_reconstruction_close(vi):
         go, _ = g.reconstruct(lv, 0)
         hole_idx = np.flatnonzero(o.sets(lv)[0].ravel())
         assert_recon_close(oo, host(go), o.get_state(lv)[0], host(g.get_state(lv)[0]), hole_idx)
+
+
+# ---------------------------------------------------------------------------
+# single images (T = 1, 5x5x1 patches): 2-D image inpainting
+# ---------------------------------------------------------------------------
+
+def _edge_image():
+    c = synth.image(95, 64, 52, levels=2)
+    c.mask[:] = 0
+    c.mask[0, 0:7, 0:9] = 1
+    c.mask[0, 44:52, 50:64] = 1
+    return c
+
+
+IMAGES = {
+    "img2": lambda: (synth.image(93, 77, 61, frac=0.05, levels=2), 2),
+    "img3": lambda: (synth.image(94, 160, 120, frac=0.04, levels=3, kind="box"), 3),
+    "imgedge": lambda: (_edge_image(), 2),
+}
+P2 = dict(patch=(5, 5, 1))
+
+
+@pytest.mark.parametrize("name", list(IMAGES))
+def test_image_create_and_search_bitexact(vi, name):
+    clip, L = IMAGES[name]()
+    o, g = make_pair(vi, clip, levels=L, seed=7, **P2)
+    for lv in range(L):
+        assert o.info(lv) == g.info(lv)
+        for a, b in zip(o.sets(lv), g.sets(lv)):
+            assert np.array_equal(a, host(b)), lv
+        for a, b in zip(o.get_state(lv), g.get_state(lv)):
+            assert np.array_equal(a, host(b)), lv
+        rgbt, cand = _forced_state(o, lv, 500 + lv)
+        o.set_state(lv, rgbt=rgbt, cand=cand)
+        g.set_state(lv, rgbt=rgbt, cand=cand)
+        o.nnf_search(lv, 1)
+        g.nnf_search(lv, 1)
+        for a, b in zip(o.get_state(lv)[1:], g.get_state(lv)[1:]):
+            assert np.array_equal(a, host(b)), lv
+
+
+@pytest.mark.parametrize("name", list(IMAGES))
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_image_reconstruct_parity(vi, name, mode):
+    clip, L = IMAGES[name]()
+    o, g = make_pair(vi, clip, levels=L, seed=9, **P2)
+    for lv in range(L):
+        rgbt, cand = _forced_state(o, lv, 600 + lv)
+        o.set_state(lv, rgbt=rgbt, cand=cand)
+        o.nnf_search(lv, 0)
+        g.set_state(lv, *o.get_state(lv))
+        oo, os_ = o.reconstruct(lv, mode)
+        go, gs = g.reconstruct(lv, mode)
+        o_r = o.get_state(lv)[0]
+        g_r = host(g.get_state(lv)[0])
+        hole_idx = np.flatnonzero(o.sets(lv)[0].ravel())
+        if mode == 0:
+            assert_recon_close(oo, host(go), o_r, g_r, hole_idx)
+        else:
+            assert np.array_equal(o_r, g_r)
+            assert os_ == int(host(gs)[0])
+
+
+@pytest.mark.parametrize("name", list(IMAGES))
+def test_image_inpaint_mean_end_to_end_bitexact(vi, name):
+    clip, L = IMAGES[name]()
+    o, g = make_pair(vi, clip, levels=L, seed=12, recon_mode=1, **P2)
+    assert np.array_equal(o.inpaint(), host(g.inpaint()))
+
+
+def test_image_weighted_end_to_end(vi):
+    clip, L = IMAGES["img3"]()
+    o, g = make_pair(vi, clip, levels=L, seed=12, **P2)
+    a = o.inpaint()
+    b = host(g.inpaint())
+    keep = clip.mask == 0
+    assert np.array_equal(b[keep], clip.video[keep])
+    same = (a[~keep] == b[~keep]).all(axis=-1).mean()
+    print(f"[img3] un-forced weighted end-to-end: {100 * same:.2f} % hole pixels identical")
+    assert same > 0.9
+
+
+def test_image_parameter_errors(vi):
+    clip, _ = IMAGES["img2"]()
+    v = dev(clip.occluded_input())
+    m = dev(clip.mask)
+    with pytest.raises(vi.ViError):  # 5x5x1 patches on a video
+        vi.Clip(dev(np.repeat(clip.occluded_input(), 3, 0)), dev(np.repeat(clip.mask, 3, 0)),
+                levels=1, **P2)
+    with pytest.raises(vi.ViError):  # no temporal subsampling of one image
+        vi.Clip(v, m, levels=2, temporal_subsample=1, **P2)
+    with pytest.raises(vi.ViError):  # 5x5x5 patches on one image
+        vi.Clip(v, m, levels=2)
