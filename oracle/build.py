@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(HERE, f) for f in ("vio.c", "vio_align.c")]
+    srcs = [os.path.join(HERE, f) for f in ("vio.c", "vio_align.c", "vio_appb.c")]
     tmp = LIB + ".tmp"
     cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
            "-Wall", "-Wextra", "-Wno-unused-parameter", *srcs, "-o", tmp, "-lm"]

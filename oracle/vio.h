@@ -167,6 +167,16 @@ int vio_align_warp(const uint8_t* rgb, const uint8_t* mask, int32_t W, int32_t H
 int vio_align_unwarp(const uint8_t* aligned, const uint8_t* rgb, const uint8_t* mask, int32_t W,
                      int32_t H, int32_t T, const double* M, uint8_t* out_rgb);
 
+/* ---- The textured-patch experiment of App. B ----
+ * For every reference patch W_r (ref [n_ref][pt][ph][pw], grey values) and
+ * every patch V of the grey volume vol [T][H][W] that lies wholly inside
+ * it, counts[r] = the number of V with SSD(W_r, V) < SSD(W_r, Z), Z the
+ * constant patch of value mu (0..255).  A volume smaller than the patch
+ * has no candidates (all counts 0). */
+int vio_closer_than_constant(const uint8_t* ref, int32_t n_ref, const uint8_t* vol, int32_t W,
+                             int32_t H, int32_t T, int32_t pw, int32_t ph, int32_t pt,
+                             int32_t mu, uint64_t* counts);
+
 /* E = sum over H~^level of SSD(q, cand(q)) (unnormalised). */
 int64_t vio_energy(const vio_ctx* ctx, int32_t level);
 

@@ -86,6 +86,9 @@ def lib():
         L.vio_affine_inverse.argtypes = [f64p, f64p]
         L.vio_align_warp.argtypes = [u8p, u8p, C.c_int32, C.c_int32, C.c_int32, f64p, u8p, u8p]
         L.vio_align_unwarp.argtypes = [u8p, u8p, u8p, C.c_int32, C.c_int32, C.c_int32, f64p, u8p]
+        L.vio_closer_than_constant.argtypes = [u8p, C.c_int32, u8p, C.c_int32, C.c_int32,
+                                               C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                               C.c_int32, P(C.c_uint64)]
         _LIB = L
     return _LIB
 
@@ -331,4 +334,21 @@ def align_unwarp(aligned, video, mask, M):
     _check("vio_align_unwarp", lib().vio_align_unwarp(
         _ptr(a, C.c_uint8), _ptr(v, C.c_uint8), _ptr(m, C.c_uint8), W, H, T,
         _ptr(Mm, C.c_double), _ptr(out, C.c_uint8)))
+    return out
+
+
+# ------------------------------------------------ App. B textured-patch count
+
+def closer_than_constant(ref, vol, patch, mu=128):
+    """counts[r]: patches V of the grey volume ``vol`` [T][H][W] with
+    SSD(ref[r], V) < SSD(ref[r], Z), Z the constant patch ``mu``; ``ref`` is
+    [n][pt][ph][pw] (or [n][N]) and ``patch`` = (pw, ph, pt)."""
+    pw, ph, pt = patch
+    r = np.ascontiguousarray(ref, np.uint8).reshape(-1, pw * ph * pt)
+    v = np.ascontiguousarray(vol, np.uint8)
+    T, H, W = v.shape
+    out = np.zeros(r.shape[0], np.uint64)
+    _check("vio_closer_than_constant", lib().vio_closer_than_constant(
+        _ptr(r, C.c_uint8), r.shape[0], _ptr(v, C.c_uint8), W, H, T, pw, ph, pt, mu,
+        _ptr(out, C.c_uint64)))
     return out

@@ -316,6 +316,16 @@ def image(seed: int, W: int, H: int, frac: float = 0.04, levels: int = 2, n_obj:
     return small(seed, W, H, 1, frac=frac, levels=levels, n_obj=n_obj, kind=kind, noise=noise)
 
 
+def noise(seed: int, shape, sigma2: float = 25.0, mean: int = 128) -> np.ndarray:
+    """Grey white noise for the textured-patch experiment of App. B: i.i.d.
+    centred normal values of variance sigma2 (25 grey levels squared in the
+    paper's table) around ``mean``, rounded half up to integers and clipped
+    to 0..255 (at sigma = 5 the clip is never reached).  ``shape`` is
+    [T][H][W] for a volume or [n][pt][ph][pw] for a list of patches."""
+    rng = np.random.default_rng(seed)
+    return _u8(mean + math.sqrt(sigma2) * rng.standard_normal(tuple(shape)))
+
+
 def served_trace(duration_s: float = 120.0, rate: float = 4.0, seed: int = 2000,
                  sd_frac: float = 0.10):
     """Poisson arrivals: list of (arrival_time_s, kind, seed) where kind is
