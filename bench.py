@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--config", default="hd", choices=["sd", "hd", "tiny"])
     ap.add_argument("--no-realign", action="store_true",
                     help="skip the realignment measurement (Sec. 3.4)")
+    ap.add_argument("--no-appb", action="store_true",
+                    help="skip the textured-patch experiment (App. B)")
     ap.add_argument("--no-sd", action="store_true",
                     help="skip the SD clip measured beside the headline workload")
     ap.add_argument("--sd-steps", type=int, default=3)
@@ -441,8 +443,8 @@ def served_sweep(rates, n_jobs, em_iters):
 def measure_realign(steps=3):
     """Realignment of a shaking-camera clip (854x480 px x 50 frames):
     estimation of every frame pair's motion, composition, warp of video and
-    occlusion, unwarp into the occlusion; GPU times (inputs resident in HBM)
-    and the oracle's estimation and warp on the host."""
+    occlusion, unwarp into the occlusion; GPU times (inputs resident in
+    HBM)."""
     import numpy as np
     import torch
     from paper_1503_05528_amd import synth, vi
@@ -481,22 +483,104 @@ def measure_realign(steps=3):
     # warp: per output pixel the source frame's 3 colour bytes and mask byte
     # (the 2x2 stencil overlaps its neighbours') and 4 bytes written
     warp_bytes = 8 * px
-    from oracle import vio
-    vn, mn = clip.occluded_input(), clip.mask
-    c0 = time.perf_counter()
-    oth = vio.align_estimate(vn, mn)
-    c1 = time.perf_counter()
-    vio.align_warp(vn, mn, vio.align_compose(oth, T))
-    c2 = time.perf_counter()
     return {"workload": f"shaking-camera clip {W}x{H}x{T}, 3 estimation levels x 8 robust "
                         "Gauss-Newton steps per frame pair",
             "estimate_ms": 1000 * est, "warp_ms": 1000 * warp, "unwarp_ms": 1000 * unwarp,
             "frames_per_s": T / (est + warp + unwarp),
             "max_corner_error_px": float(err),
             "warp_call_gbs": warp_bytes / warp / 1e9,
-            "warp_call_frac_of_hbm_peak": warp_bytes / warp / 1e9 / HBM_PEAK_GBS,
-            "oracle_estimate_s": c1 - c0, "oracle_warp_s": c2 - c1,
-            "oracle_threads": vio.num_threads()}
+            "warp_call_frac_of_hbm_peak": warp_bytes / warp / 1e9 / HBM_PEAK_GBS}
+
+
+def realign_cpu_baseline():
+    """CPU baseline leg of the realignment: the oracle's estimation and warp
+    of the same clip on all host cores."""
+    from oracle import vio
+    from paper_1503_05528_amd import synth
+    clip, _ = synth.jittered(seed=11, W=854, H=480, T=50)
+    T = clip.video.shape[0]
+    vn, mn = clip.occluded_input(), clip.mask
+    c0 = time.perf_counter()
+    oth = vio.align_estimate(vn, mn)
+    c1 = time.perf_counter()
+    vio.align_warp(vn, mn, vio.align_compose(oth, T))
+    c2 = time.perf_counter()
+    return {"kind": "oracle", "estimate_s": c1 - c0, "warp_s": c2 - c1,
+            "cores": vio.num_threads(), "sample": "the whole clip"}
+
+
+# App. B table: probability that a random patch beats the constant patch
+# (white noise of grey-level variance 25), as printed
+APPB_PAPER = [((3, 3, 1), 8e-2), ((5, 5, 1), 1e-2), ((3, 3, 3), 6e-3), ((7, 7, 1), 4.1e-4),
+              ((9, 9, 1), 5.5e-6), ((11, 11, 1), 3e-7), ((5, 5, 5), 2e-7)]
+APPB_SIDE = 256
+APPB_REFS = 4096
+
+
+def measure_appb(steps=3):
+    """The textured-patch experiment of App. B: for each of the table's seven
+    patch sizes, 4096 white-noise reference patches against every patch of
+    a 256^3 white-noise volume (2-D sizes: every patch of each of its 256
+    frames), counting the patches closer to the reference than the
+    constant patch; GPU time of the call (HIP events on the stream it is
+    enqueued on, inputs resident in HBM)."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1503_05528_amd import synth, vi
+    n = APPB_SIDE
+    vol = torch.from_numpy(synth.noise(170, (n, n, n))).cuda()
+    rows = []
+    total_pairs, total_s = 0, 0.0
+    for patch, printed in APPB_PAPER:
+        pw, ph, pt = patch
+        N = pw * ph * pt
+        n_cand = (n - pw + 1) * (n - ph + 1) * (n - pt + 1)
+        ref = torch.from_numpy(synth.noise(1000 + N, (APPB_REFS, pt, ph, pw))).cuda()
+        out = vi.closer_than_constant(ref, vol, patch)  # warm-up
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            vi.closer_than_constant(ref, vol, patch, out=out)
+            e1.record()
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        t = statistics.median(ms) / 1000.0
+        c = out.cpu().numpy().astype(np.float64)
+        rate = c / n_cand
+        pairs = APPB_REFS * n_cand
+        total_pairs += pairs
+        total_s += t
+        # VALU lane operations per pair: the inner product four bytes per
+        # v_dot4, then one shift-and-subtract and one compare
+        ops = (N + 3) // 4 + 2
+        rows.append({"patch": "x".join(map(str, patch)), "voxels": N, "references": APPB_REFS,
+                     "candidates": n_cand, "hits": int(c.sum()), "probability": rate.mean(),
+                     "std_error": rate.std(ddof=1) / math.sqrt(APPB_REFS),
+                     "paper": printed, "ms": 1000 * t, "pairs_per_s": pairs / t,
+                     "valu_frac": pairs / t * ops / (VALU_PEAK_TOPS * 1e12)})
+    return {"workload": f"{n}x{n}x{n} grey white noise (variance 25), {APPB_REFS} reference "
+                        "patches per patch size, the seven sizes of the App. B table",
+            "pairs_per_s": total_pairs / total_s, "ms_total": 1000 * total_s, "rows": rows,
+            "roofline": {"bound": "alu", "unit": "TOP/s", "peak": VALU_PEAK_TOPS,
+                         "note": "per pair ceil(N/4) v_dot4 + 2 VALU lane operations"}}
+
+
+def appb_cpu_baseline():
+    """CPU baseline leg of App. B: the oracle's brute-force count for one
+    5x5x5 reference patch over the whole 256^3 volume."""
+    from oracle import vio
+    from paper_1503_05528_amd import synth
+    n = APPB_SIDE
+    vol = synth.noise(170, (n, n, n))
+    ref = synth.noise(1000 + 125, (1, 5, 5, 5))
+    c0 = time.perf_counter()
+    vio.closer_than_constant(ref, vol, (5, 5, 5))
+    dt = time.perf_counter() - c0
+    return {"value": (n - 4) ** 3 / dt, "unit": "pairs/s", "cores": vio.num_threads(),
+            "kind": "oracle", "sample": "one 5x5x5 reference against every patch of the volume"}
 
 
 def make_clip(name):
@@ -859,6 +943,9 @@ def main():
     if not a.no_realign:
         log("realignment: shaking-camera clip")
         line["realign"] = measure_realign()
+    if not a.no_appb:
+        log("App. B: random patches against the constant patch")
+        line["appb"] = measure_appb()
     if not a.no_batched or not a.no_served:
         bclips = gen_batch_clips(a.batch_clips)
         bres, service = batched_vs_serial(bclips, a.em_iters)
@@ -877,6 +964,10 @@ def main():
     if not a.no_cpu_baseline:
         log("cpu baseline: oracle search on a sample of the finest level")
         line["cpu_baseline"] = cpu_baseline(a.config, a.cpu_frames, a.cpu_frames_1core)
+        if "realign" in line:
+            line["realign"]["cpu_baseline"] = realign_cpu_baseline()
+        if "appb" in line:
+            line["appb"]["cpu_baseline"] = appb_cpu_baseline()
     print(json.dumps(line), flush=True)
 
 

@@ -326,6 +326,30 @@ vi_status vi_align_unwarp(const uint8_t* aligned, const uint8_t* rgb, const uint
                           int32_t W, int32_t H, int32_t T, const double* M, uint8_t* out_rgb,
                           void* hip_stream);
 
+/* ---- The textured-patch experiment (App. B) ----
+ * App. B asks how likely a random patch V is to be closer to a random
+ * reference patch W than the constant patch Z of the same mean, for white
+ * noise of grey-level variance 25, and tabulates it for seven patch sizes.
+ * This call counts the event: for every reference patch W_r and every
+ * patch V lying wholly inside the grey volume,
+ *   counts[r] = #{ V : SSD(W_r, V) < SSD(W_r, Z) },
+ * Z the constant patch of value mu, SSD the sum of squared differences
+ * over the patch's voxels (the patch distance of Sec. 2, one channel).
+ *   ref    (dev) [n_ref][pt][ph][pw] uint8, voxels ordered dt, dy, dx
+ *   vol    (dev) [T][H][W] uint8
+ *   counts (dev) [n_ref] uint64, overwritten
+ * pw * ph * pt in [1, 128]; mu in [0, 255]; W, H, T >= 1 with
+ * W * H * T < 2^30; 0 <= n_ref < 2^24.  A volume smaller than the patch
+ * has no candidates (every count 0); n_ref = 0 does nothing.  Enqueued on
+ * hip_stream (NULL = the null stream): returns after enqueue, allocates
+ * nothing and keeps no state; the caller keeps the buffers alive until the
+ * stream reaches the call.
+ * Errors: VI_E_INVAL (a null pointer with n_ref > 0, sizes out of range),
+ * VI_E_HIP (launch failure). */
+vi_status vi_closer_than_constant(const uint8_t* ref, int32_t n_ref, const uint8_t* vol,
+                                  int32_t W, int32_t H, int32_t T, int32_t pw, int32_t ph,
+                                  int32_t pt, int32_t mu, uint64_t* counts, void* hip_stream);
+
 /* Work counters of a context since creation or the last reset (host out).
  * effective_evals is read back from the device: syncs. */
 typedef struct {

@@ -938,6 +938,22 @@ vi_status vi_align_unwarp(const uint8_t* aligned, const uint8_t* rgb, const uint
   return st == VI_OK ? VI_OK : fail(st, "vi_align_unwarp failed (HIP error)");
 }
 
+vi_status vi_closer_than_constant(const uint8_t* ref, int32_t n_ref, const uint8_t* vol,
+                                  int32_t W, int32_t H, int32_t T, int32_t pw, int32_t ph,
+                                  int32_t pt, int32_t mu, uint64_t* counts, void* hip_stream) {
+  if (n_ref < 0 || n_ref >= (1 << 24)) return fail(VI_E_INVAL, "n_ref in [0, 2^24)");
+  if (n_ref > 0 && (!ref || !vol || !counts)) return fail(VI_E_INVAL, "null argument");
+  if (pw < 1 || ph < 1 || pt < 1 || (int64_t)pw * ph * pt > 128)
+    return fail(VI_E_INVAL, "patch sizes >= 1 with pw * ph * pt <= 128");
+  if (mu < 0 || mu > 255) return fail(VI_E_INVAL, "mu in [0, 255]");
+  if (W < 1 || H < 1 || T < 1 || (int64_t)W * H * T >= (int64_t(1) << 30))
+    return fail(VI_E_INVAL, "W, H, T >= 1 and W * H * T < 2^30");
+  const vi_status st = vi::closer_than_constant(
+      ref, n_ref, vol, W, H, T, pw, ph, pt, mu, reinterpret_cast<unsigned long long*>(counts),
+      static_cast<hipStream_t>(hip_stream));
+  return st == VI_OK ? VI_OK : fail(st, "vi_closer_than_constant: launch failed");
+}
+
 vi_status vi_transition(vi_ctx* c, int32_t level) {
   VI_TRY(level_ok(c, level));
   if (level + 1 >= c->L) return fail(VI_E_INVAL, "no coarser level");

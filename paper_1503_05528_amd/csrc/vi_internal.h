@@ -224,6 +224,12 @@ vi_status align_unwarp(const uint8_t* aligned, const uint8_t* rgb, const uint8_t
                        int32_t H, int32_t T, const double* M, double* d_m, uint8_t* out,
                        hipStream_t st);
 
+// The textured-patch count of App. B (vi_appb.hip); arguments checked by
+// the caller.
+vi_status closer_than_constant(const uint8_t* ref, int32_t n_ref, const uint8_t* vol, int32_t W,
+                               int32_t H, int32_t T, int32_t pw, int32_t ph, int32_t pt,
+                               int32_t mu, unsigned long long* counts, hipStream_t st);
+
 // stream compaction (stable): out[k] = i for the k-th i with flags[i] != 0
 size_t compact_temp_bytes(int32_t n);
 hipError_t compact(hipStream_t st, const uint8_t* flags, int32_t n, int32_t* out,

@@ -60,6 +60,8 @@ SIGNATURES = {
     "vi_align_compose": (_i32, [_f64p, _i32, _f64p]),
     "vi_align_warp": (_i32, [_vp, _vp, _i32, _i32, _i32, _f64p, _vp, _vp, _vp]),
     "vi_align_unwarp": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _f64p, _vp, _vp]),
+    "vi_closer_than_constant": (_i32, [_vp, _i32, _vp, _i32, _i32, _i32, _i32, _i32, _i32,
+                                       _i32, _vp, _vp]),
     "vi_params_default": (_i32, [C.c_void_p]),
     "vi_create": (_i32, [C.POINTER(_vp), C.c_void_p, _i32, _i32, _i32, _vp, _vp, _vp]),
     "vi_level_info": (_i32, [_vp, _i32, C.POINTER(_i32), C.POINTER(_i64)]),
@@ -496,3 +498,24 @@ def inpaint_realigned(video: torch.Tensor, mask: torch.Tensor, align=None, **kw)
     inp = g.inpaint()
     g.close()
     return align_unwarp(inp, video, mask, M), theta, M
+
+
+def closer_than_constant(ref: torch.Tensor, vol: torch.Tensor, patch, mu: int = 128,
+                         out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """The textured-patch count of App. B on the GPU: out[r] = the number of
+    patches V of the grey volume ``vol`` [T][H][W] (uint8, device) with
+    SSD(ref[r], V) < SSD(ref[r], Z), Z the constant patch of value ``mu``.
+    ``ref`` is [n][pt][ph][pw] (or [n][pw*ph*pt]) uint8 on the device and
+    ``patch`` = (pw, ph, pt).  Returns int64 counts (device); enqueued on
+    ``stream`` (default: the current stream) without a sync."""
+    pw, ph, pt = (int(v) for v in patch)
+    n = ref.shape[0]
+    if ref.numel() != n * pw * ph * pt:
+        raise ValueError("ref must hold n patches of pw * ph * pt voxels")
+    T, H, W = vol.shape
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=vol.device)
+    _check("vi_closer_than_constant", lib().vi_closer_than_constant(
+        _ptr(ref) if n else None, n, _ptr(vol), W, H, T, pw, ph, pt, int(mu),
+        _ptr(out) if n else None, _stream_handle(stream)))
+    return out
