@@ -38,6 +38,10 @@ typedef struct {
   int32_t* dist;
   uint8_t* nvox;
   int searched;    /* a shift map exists on H~^l */
+  /* dimensionality-reduced distance (Sec. 5): basis and voxel features */
+  int32_t red_d;   /* 0: the exact distance */
+  int16_t* redQ;   /* [red_d][5 x patch voxels] */
+  int32_t* feat;   /* [V][red_d] */
 } level_t;
 
 struct vio_ctx {
@@ -126,6 +130,7 @@ static int inside(const level_t* L, int64_t x, int64_t y, int64_t t) {
 static void free_level(level_t* L) {
   free(L->rgbt); free(L->hole); free(L->dsrc); free(L->htil); free(L->dlist);
   free(L->cand); free(L->dist); free(L->nvox);
+  free(L->redQ); free(L->feat);
   memset(L, 0, sizeof(*L));
 }
 
@@ -449,6 +454,63 @@ int64_t vio_patch_ssd(const vio_ctx* ctx, int32_t level, int64_t p, int64_t c,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Dimensionality-reduced patch space (Sec. 5 suggests it as an             */
+/* acceleration; the construction is this implementation's reading).        */
+/*                                                                          */
+/* The patch vector x(p) lists, for the offsets o in the order dt, dy, dx,  */
+/* the channels R, G, B, Tx, Ty of the voxel p + o, its coordinates clamped */
+/* to the volume.  With w = 1 on colour and sqrt(lambda) on texture, the    */
+/* squared distance of the weighted vectors w x is the patch distance.  A   */
+/* basis Q [d][dim] of integers (a linear map scaled by 256) gives the      */
+/* features f_k(p) = floor((sum_i Q[k][i] x_i(p) + 128) / 256), and the     */
+/* reduced distance of p and c is sum_k (f_k(p) - f_k(c))^2, saturated at   */
+/* 2^31 - 1.                                                                */
+/* ------------------------------------------------------------------------ */
+static int64_t clampi(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+static void features_of(const vio_ctx* ctx, const level_t* L, int64_t p, int32_t* f) {
+  const int hx = ctx->prm.patch[0] / 2, hy = ctx->prm.patch[1] / 2, ht = ctx->prm.patch[2] / 2;
+  const int dim = 5 * ctx->prm.patch[0] * ctx->prm.patch[1] * ctx->prm.patch[2];
+  int32_t px, py, pt;
+  unlin(L, p, &px, &py, &pt);
+  for (int k = 0; k < L->red_d; ++k) {
+    const int16_t* q = L->redQ + (int64_t)k * dim;
+    int64_t acc = 0;
+    int i = 0;
+    for (int dt = -ht; dt <= ht; ++dt)
+      for (int dy = -hy; dy <= hy; ++dy)
+        for (int dx = -hx; dx <= hx; ++dx) {
+          const int64_t a = lin(L, clampi(px + dx, 0, L->W - 1), clampi(py + dy, 0, L->H - 1),
+                                clampi(pt + dt, 0, L->T - 1));
+          for (int ch = 0; ch < 5; ++ch, ++i) acc += (int64_t)q[i] * L->rgbt[5 * a + ch];
+        }
+    /* floor division by 256 of acc + 128 */
+    const int64_t v = acc + 128;
+    f[k] = (int32_t)(v >= 0 ? v / 256 : -((-v + 255) / 256));
+  }
+}
+
+static int64_t red_dist(const level_t* L, int64_t p, int64_t c) {
+  const int32_t* a = L->feat + p * L->red_d;
+  const int32_t* b = L->feat + c * L->red_d;
+  int64_t s = 0;
+  for (int k = 0; k < L->red_d; ++k) {
+    const int64_t e = (int64_t)a[k] - b[k];
+    s += e * e;
+    if (s > 2147483647) return 2147483647;
+  }
+  return s;
+}
+
+/* the distance a search compares: reduced when the level has a basis and
+   the search is the unmasked one of the EM loop, else the exact one */
+static int64_t search_dist(const vio_ctx* ctx, const level_t* L, int red, int64_t p, int64_t c,
+                           const uint8_t* cmask, int32_t* n_out) {
+  if (red) return red_dist(L, p, c);
+  return ssd(ctx, L, p, c, cmask, n_out);
+}
+
+/* ------------------------------------------------------------------------ */
 /* ANN search (Sec. 3.1, Alg. 1), made synchronous.                         */
 /*                                                                          */
 /* Random numbers: Philox4x64-10 with key (seed, 0) and counter             */
@@ -530,6 +592,13 @@ static void search(vio_ctx* ctx, int32_t level, const uint8_t* tmask, const uint
       if (tmask[i]) S[k++] = i;
   }
   const uint64_t key[2] = {P->seed, 0};
+  /* the reduced distance: the targets' features on the current video (the
+     sources' patches never change within a level) */
+  const int red = L->red_d > 0 && cmask == NULL;
+  if (red) {
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t j = 0; j < nS; ++j) features_of(ctx, L, S[j], L->feat + S[j] * L->red_d);
+  }
 
   /* step 0: initialisation of missing / invalid matches, re-evaluation */
 #pragma omp parallel for schedule(dynamic, 256)
@@ -542,8 +611,8 @@ static void search(vio_ctx* ctx, int32_t level, const uint8_t* tmask, const uint
       L->cand[p] = (int32_t)L->dlist[draw_below(w[0], L->nD)];
     }
     int32_t n = 0;
-    L->dist[p] = (int32_t)ssd(ctx, L, p, L->cand[p], cmask, &n);
-    L->nvox[p] = (uint8_t)n;
+    L->dist[p] = (int32_t)search_dist(ctx, L, red, p, L->cand[p], cmask, &n);
+    if (!red) L->nvox[p] = (uint8_t)n;
   }
 
   const int32_t r_max = L->W > L->H ? (L->W > L->T ? L->W : L->T) : (L->H > L->T ? L->H : L->T);
@@ -576,7 +645,7 @@ static void search(vio_ctx* ctx, int32_t level, const uint8_t* tmask, const uint
           if (!inside(L, cx, cy, ct)) continue;
           int64_t c = lin(L, cx, cy, ct);
           if (!L->dsrc[c]) continue;
-          int64_t d = ssd(ctx, L, p, c, cmask, NULL);
+          int64_t d = search_dist(ctx, L, red, p, c, cmask, NULL);
           if (d < best_d) { best_d = d; best_c = c; }
         }
         ncand[p] = (int32_t)best_c;
@@ -593,11 +662,22 @@ static void search(vio_ctx* ctx, int32_t level, const uint8_t* tmask, const uint
       int64_t p = S[j];
       int64_t c = rs_candidate(ctx, level, p, L->cand[p], R, step, k);
       if (!L->dsrc[c]) continue;
-      int64_t d = ssd(ctx, L, p, c, cmask, NULL);
+      int64_t d = search_dist(ctx, L, red, p, c, cmask, NULL);
       if (d < L->dist[p]) {
         L->cand[p] = (int32_t)c;
         L->dist[p] = (int32_t)d;
       }
+    }
+  }
+  /* the reduced distance only chooses the matches: every target's match
+     is evaluated with the exact distance, which the reconstruction uses */
+  if (red) {
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t j = 0; j < nS; ++j) {
+      const int64_t p = S[j];
+      int32_t n = 0;
+      L->dist[p] = (int32_t)ssd(ctx, L, p, L->cand[p], NULL, &n);
+      L->nvox[p] = (uint8_t)n;
     }
   }
   free(S);
@@ -745,6 +825,73 @@ int vio_reconstruct(vio_ctx* ctx, int32_t level, int32_t mode, float* out_f, int
   if (!L->searched) return VIO_E_STATE;
   int64_t s = reconstruct(ctx, L, L->hole, NULL, mode, out_f);
   if (absdiff) *absdiff = s;
+  return VIO_OK;
+}
+
+int vio_set_reduction(vio_ctx* ctx, int32_t level, const int16_t* Q, int32_t d) {
+  if (!ctx || level < 0 || level >= ctx->L || d < 0 || (d > 0 && !Q)) return VIO_E_INVAL;
+  level_t* L = &ctx->lv[level];
+  const int dim = 5 * ctx->prm.patch[0] * ctx->prm.patch[1] * ctx->prm.patch[2];
+  if (d > dim) return VIO_E_INVAL;
+  free(L->redQ);
+  free(L->feat);
+  L->redQ = NULL;
+  L->feat = NULL;
+  L->red_d = 0;
+  if (d == 0) return VIO_OK;
+  L->redQ = (int16_t*)malloc(sizeof(int16_t) * (size_t)d * dim);
+  L->feat = (int32_t*)malloc(sizeof(int32_t) * (size_t)d * (size_t)L->V);
+  if (!L->redQ || !L->feat) return VIO_E_NOMEM;
+  memcpy(L->redQ, Q, sizeof(int16_t) * (size_t)d * dim);
+  L->red_d = d;
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t p = 0; p < L->V; ++p) features_of(ctx, L, p, L->feat + p * d);
+  return VIO_OK;
+}
+
+int vio_features(const vio_ctx* ctx, int32_t level, int32_t* out) {
+  if (!ctx || level < 0 || level >= ctx->L || !out) return VIO_E_INVAL;
+  const level_t* L = &ctx->lv[level];
+  if (L->red_d == 0) return VIO_E_STATE;
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t p = 0; p < L->V; ++p) features_of(ctx, L, p, out + p * L->red_d);
+  return VIO_OK;
+}
+
+/* Moments of the patch vectors of a sample of the sources: every k-th
+   entry of D~ in ascending order, k = ceil(|D~| / n_max), so at most n_max
+   samples.  S1[i] = sum of x_i, S2[i][j] = sum of x_i x_j (all dim x dim
+   entries), exact integers. */
+int vio_pca_moments(const vio_ctx* ctx, int32_t level, int32_t n_max, uint64_t* S1,
+                    uint64_t* S2, int64_t* n_out) {
+  if (!ctx || level < 0 || level >= ctx->L || n_max < 1 || !S1 || !S2 || !n_out)
+    return VIO_E_INVAL;
+  const level_t* L = &ctx->lv[level];
+  const int hx = ctx->prm.patch[0] / 2, hy = ctx->prm.patch[1] / 2, ht = ctx->prm.patch[2] / 2;
+  const int dim = 5 * ctx->prm.patch[0] * ctx->prm.patch[1] * ctx->prm.patch[2];
+  const int64_t k = (L->nD + n_max - 1) / n_max;
+  memset(S1, 0, sizeof(uint64_t) * dim);
+  memset(S2, 0, sizeof(uint64_t) * (size_t)dim * dim);
+  int64_t n = 0;
+  uint8_t* x = (uint8_t*)malloc((size_t)dim);
+  if (!x) return VIO_E_NOMEM;
+  for (int64_t j = 0; k > 0 && j < L->nD; j += k, ++n) {
+    int32_t cx, cy, ct;
+    unlin(L, L->dlist[j], &cx, &cy, &ct);
+    int i = 0;
+    for (int dt = -ht; dt <= ht; ++dt)
+      for (int dy = -hy; dy <= hy; ++dy)
+        for (int dx = -hx; dx <= hx; ++dx) {
+          const int64_t a = lin(L, cx + dx, cy + dy, ct + dt);
+          for (int ch = 0; ch < 5; ++ch) x[i++] = L->rgbt[5 * a + ch];
+        }
+    for (int a = 0; a < dim; ++a) {
+      S1[a] += x[a];
+      for (int b = 0; b < dim; ++b) S2[(size_t)a * dim + b] += (uint64_t)x[a] * x[b];
+    }
+  }
+  free(x);
+  *n_out = n;
   return VIO_OK;
 }
 

@@ -167,6 +167,23 @@ int vio_align_warp(const uint8_t* rgb, const uint8_t* mask, int32_t W, int32_t H
 int vio_align_unwarp(const uint8_t* aligned, const uint8_t* rgb, const uint8_t* mask, int32_t W,
                      int32_t H, int32_t T, const double* M, uint8_t* out_rgb);
 
+/* ---- Dimensionality-reduced patch distance (Sec. 5) ----
+ * A basis Q [d][dim] (dim = 5 x patch voxels; int16, a linear map scaled
+ * by 256) for one level: the features of voxel p are
+ * f_k(p) = floor((sum_i Q[k][i] x_i(p) + 128) / 256), x(p) the patch
+ * vector (offsets dt, dy, dx; channels R, G, B, Tx, Ty; coordinates clamped
+ * to the volume), and the level's unmasked searches compare
+ * sum_k (f_k(p) - f_k(c))^2 (saturated at 2^31 - 1) instead of the patch
+ * distance; after each search every target's match is evaluated with the
+ * exact distance.  d = 0 restores the exact search. */
+int vio_set_reduction(vio_ctx* ctx, int32_t level, const int16_t* Q, int32_t d);
+/* the features of every voxel of the level: out [V][d] */
+int vio_features(const vio_ctx* ctx, int32_t level, int32_t* out);
+/* Exact moments of the patch vectors of every k-th source (D~ ascending,
+ * k = ceil(|D~| / n_max)): S1 [dim], S2 [dim][dim], *n = samples. */
+int vio_pca_moments(const vio_ctx* ctx, int32_t level, int32_t n_max, uint64_t* S1,
+                    uint64_t* S2, int64_t* n);
+
 /* ---- The textured-patch experiment of App. B ----
  * For every reference patch W_r (ref [n_ref][pt][ph][pw], grey values) and
  * every patch V of the grey volume vol [T][H][W] that lies wholly inside

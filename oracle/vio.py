@@ -86,6 +86,10 @@ def lib():
         L.vio_affine_inverse.argtypes = [f64p, f64p]
         L.vio_align_warp.argtypes = [u8p, u8p, C.c_int32, C.c_int32, C.c_int32, f64p, u8p, u8p]
         L.vio_align_unwarp.argtypes = [u8p, u8p, u8p, C.c_int32, C.c_int32, C.c_int32, f64p, u8p]
+        L.vio_set_reduction.argtypes = [C.c_void_p, C.c_int32, P(C.c_int16), C.c_int32]
+        L.vio_features.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32)]
+        L.vio_pca_moments.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(C.c_uint64),
+                                      P(C.c_uint64), P(C.c_int64)]
         L.vio_closer_than_constant.argtypes = [u8p, C.c_int32, u8p, C.c_int32, C.c_int32,
                                                C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                                C.c_int32, P(C.c_uint64)]
@@ -145,7 +149,7 @@ class Oracle:
     """One clip in the CPU oracle."""
 
     def __init__(self, video: np.ndarray, mask: np.ndarray, params: Params | None = None,
-                 **kw):
+                 reduce_dims: int = 0, reduce_samples: int = 65536, **kw):
         self.params = params if params is not None else default_params(**kw)
         T, H, W, _ = video.shape
         self.W, self.H, self.T = W, H, T
@@ -156,6 +160,10 @@ class Oracle:
                               _ptr(m, C.c_uint8))
         _check("vio_create", st)
         self.h = h
+        if reduce_dims:
+            # every level gets the PCA basis of its own source patches
+            for level in range(self.params.levels):
+                self.set_reduction(level, self.pca_basis(level, reduce_dims, reduce_samples))
 
     def close(self):
         if getattr(self, "h", None):
@@ -260,6 +268,45 @@ class Oracle:
             self.h, _ptr(E, C.c_uint8), layer, _ptr(bd, C.c_uint8), _ptr(S, C.c_uint8),
             _ptr(out, C.c_float), C.byref(n)))
         return E, bd, S, out[:int(n.value)]
+
+    @property
+    def patch_dim(self):
+        return 5 * self.params.patch[0] * self.params.patch[1] * self.params.patch[2]
+
+    def pca_moments(self, level, n_max=65536):
+        """(S1 [dim], S2 [dim][dim], n): exact moments of the sampled source
+        patches."""
+        dim = self.patch_dim
+        S1 = np.zeros(dim, np.uint64)
+        S2 = np.zeros((dim, dim), np.uint64)
+        n = C.c_int64(0)
+        _check("vio_pca_moments", lib().vio_pca_moments(
+            self.h, level, n_max, _ptr(S1, C.c_uint64), _ptr(S2, C.c_uint64), C.byref(n)))
+        return S1, S2, int(n.value)
+
+    def pca_basis(self, level, d, n_max=65536):
+        """Q [d][dim] int16: the quantised d leading principal directions of
+        the level's source patches."""
+        from . import pca
+        S1, S2, n = self.pca_moments(level, n_max)
+        _, B = pca.basis(pca.covariance(S1, S2, n, self.params.lambda_), d)
+        return pca.quantize(B, self.params.lambda_)
+
+    def set_reduction(self, level, Q):
+        """Searches at this level compare the features of basis Q [d][dim]
+        (None: the exact distance again)."""
+        if Q is None:
+            _check("vio_set_reduction", lib().vio_set_reduction(self.h, level, None, 0))
+            return
+        q = np.ascontiguousarray(Q, np.int16)
+        _check("vio_set_reduction", lib().vio_set_reduction(self.h, level, _ptr(q, C.c_int16),
+                                                            q.shape[0]))
+
+    def features(self, level, d):
+        W, H, T = self.dims(level)
+        out = np.zeros((T, H, W, d), np.int32)
+        _check("vio_features", lib().vio_features(self.h, level, _ptr(out, C.c_int32)))
+        return out
 
     def rs_candidate(self, level, p, c0, k, step=0):
         return int(lib().vio_rs_candidate(self.h, level, int(p), int(c0), int(k),
