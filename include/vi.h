@@ -77,6 +77,14 @@ typedef struct {
                                  upsampled in time as in space), for objects
                                  that stay long behind the occlusion; the
                                  coarsest level must keep >= 5 frames */
+  int32_t reduce_dims;  /* 0 (default): searches compare whole patches.
+                           1..32: the dimensionality-reduced patch space that
+                           Sec. 5 proposes as an acceleration: at creation
+                           every level gets the reduce_dims leading principal
+                           directions of its source patches (65536 sampled
+                           sources, 64 steps of orthogonal iteration; see
+                           vi_pca_basis), and the searches of the EM loop
+                           compare those features (vi_set_reduction) */
 } vi_params;
 
 typedef struct vi_ctx vi_ctx; /* one clip: all its device state */
@@ -325,6 +333,62 @@ vi_status vi_align_warp(const uint8_t* rgb, const uint8_t* mask, int32_t W, int3
 vi_status vi_align_unwarp(const uint8_t* aligned, const uint8_t* rgb, const uint8_t* mask,
                           int32_t W, int32_t H, int32_t T, const double* M, uint8_t* out_rgb,
                           void* hip_stream);
+
+/* ---- Dimensionality-reduced patch space (Sec. 5) ----
+ * Sec. 5 proposes dimensionality-reducing transformations of the patch space
+ * to accelerate the method without fixing one.  Here: the patch vector x(p)
+ * of a voxel lists, offset by offset (dt, dy, dx) of the patch, the channels
+ * R, G, B, Tx, Ty of voxel p + o, its coordinates clamped to the volume
+ * (dim = 5 x patch voxels: 625, or 125 for 5x5x1 patches).  A basis Q
+ * [d][dim] of 16-bit integers (a linear map scaled by 256) defines the
+ * features f_k(p) = floor((sum_i Q[k][i] x_i(p) + 128) / 256), and the
+ * reduced distance sum_k (f_k(p) - f_k(c))^2 (saturated at 2^31 - 1).
+ * With Q = rint(256 w_i b_ik), w = 1 on colour and sqrt(lambda) on texture
+ * and b the principal directions of the weighted patch vectors, the reduced
+ * distance approximates the patch distance (Secs. 2 and 3.3) with d instead
+ * of dim coordinates.
+ *
+ * vi_set_reduction: the level's searches of the EM loop (vi_nnf_search,
+ * vi_inpaint_level, vi_inpaint) compare reduced distances: each search first
+ * computes the features of its targets on the current video (the sources'
+ * patches never change at a level), and afterwards evaluates every target's
+ * match with the exact distance, which the reconstruction uses.  The onion
+ * peel keeps the exact partial distance.  Q (host) [d][dim]; d in [1, 32],
+ * or 0 to return to the exact distance (Q unused).  Computes the features
+ * of every voxel; syncs.  Contexts with a reduced level cannot join a batch.
+ * Errors: VI_E_INVAL (d out of range, null Q, a row with
+ * sum |Q[k][i]| x 255 + 128 >= 2^31), VI_E_STATE (the clip is in a batch),
+ * VI_E_NOMEM. */
+vi_status vi_set_reduction(vi_ctx* ctx, int32_t level, const int16_t* Q, int32_t d);
+
+/* The features of every voxel of the level as last computed (after
+ * vi_set_reduction: all voxels on the video of that moment; a search
+ * refreshes its targets'): out (dev) [T][H][W][d] int32, d the level's
+ * feature count (checked).  Enqueued.
+ * Errors: VI_E_INVAL (null out, d not the level's count), VI_E_STATE (no
+ * reduction at the level). */
+vi_status vi_features(const vi_ctx* ctx, int32_t level, int32_t d, int32_t* out);
+
+/* Exact moments of the patch vectors of every k-th source of the level (D~
+ * in ascending linear order, k = ceil(|D~| / n_max), so n <= n_max samples):
+ * S1 (host) [dim] sums, S2 (host) [dim][dim] sums of products.  Syncs.
+ * n_max in [1, 2^20].  Errors: VI_E_INVAL, VI_E_NOMEM, VI_E_HIP. */
+vi_status vi_pca_moments(vi_ctx* ctx, int32_t level, int32_t n_max, uint64_t* S1, uint64_t* S2,
+                         int64_t* n);
+
+/* The PCA basis of the level's source patches: from the moments above, the
+ * covariance C_ij = (w_i w_j)(S2_ij / n - (S1_i / n)(S1_j / n)) of the
+ * weighted vectors in double precision, then `iters` steps of orthogonal
+ * iteration (d columns rounded up to a multiple of 4, fixed pseudo-random
+ * start, classical Gram-Schmidt applied twice), and Q[k][i] =
+ * rint(256 w_i b_ik) for the first d columns.  Q (host) [d][dim];
+ * variance (host) [d] or NULL: b_k' C b_k, the variance each direction
+ * captures.  Does not change the level's reduction.  Syncs.
+ * d in [1, 32], n_max in [1, 2^20], iters in [0, 10000].
+ * Errors: VI_E_INVAL, VI_E_STATE (the clip is in a batch), VI_E_NOMEM,
+ * VI_E_HIP. */
+vi_status vi_pca_basis(vi_ctx* ctx, int32_t level, int32_t d, int32_t n_max, int32_t iters,
+                       int16_t* Q, double* variance);
 
 /* ---- The textured-patch experiment (App. B) ----
  * App. B asks how likely a random patch V is to be closer to a random

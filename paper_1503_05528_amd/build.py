@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvi.so")
-SOURCES = ["vi_kernels.hip", "vi_align.hip", "vi_appb.hip", "vi_api.cpp", "vi_pool.cpp"]
+SOURCES = ["vi_kernels.hip", "vi_align.hip", "vi_appb.hip", "vi_reduce.hip", "vi_api.cpp", "vi_pool.cpp"]
 ARCH = os.environ.get("VI_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

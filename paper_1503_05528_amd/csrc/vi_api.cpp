@@ -52,6 +52,11 @@ struct Level {
   // the reconstruction marks) changed the state: the next one may skip
   bool recon_ok = false;
   int32_t recon_last = -1;
+  // dimensionality-reduced patch space: basis (transposed, [dim][kMaxRed]
+  // int16), features [V][d.rd], number of features in use
+  int16_t* redQt = nullptr;
+  int32_t* feat = nullptr;
+  int32_t red_n = 0;
 };
 
 }  // namespace
@@ -164,6 +169,9 @@ void prof_end(vi_ctx* c, int r, int32_t kind, int32_t level, int64_t units,
 
 int64_t per_target_evals(const vi_params& p, int32_t rmax);
 
+// coordinates of a patch vector: 5 channels per voxel
+int32_t patch_dim(const vi_params& p) { return 5 * p.patch[0] * p.patch[1] * p.patch[2]; }
+
 vi_status check_params(const vi_params* p) {
   if (!p) return fail(VI_E_INVAL, "null params");
   if (p->abi_version != 1) return fail(VI_E_INVAL, "abi_version must be 1");
@@ -184,6 +192,8 @@ vi_status check_params(const vi_params* p) {
     return fail(VI_E_INVAL, "recon_mode must be WEIGHTED or MEAN");
   if (p->temporal_subsample != 0 && p->temporal_subsample != 1)
     return fail(VI_E_INVAL, "temporal_subsample must be 0 or 1");
+  if (p->reduce_dims < 0 || p->reduce_dims > vi::kMaxRed)
+    return fail(VI_E_INVAL, "reduce_dims must be in [0, 32]");
   return VI_OK;
 }
 
@@ -270,8 +280,18 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
   A.evals = ev_init;
   A.nin = d.nnf0;
   A.nout = d.nnf0;
-  int r = prof_begin(c, VI_K_INIT);
-  vi::launch_s0(c->st, d, A);
+  // the reduced distance (unmasked searches of a level with a basis): the
+  // targets' features on the current video first
+  const bool red = d.rd > 0 && !excl;
+  int r;
+  if (red) {
+    r = prof_begin(c, VI_K_OTHER);
+    vi::launch_features(c->st, d, lv.redQt, patch_dim(c->prm), d.rd, tlist, nS, lv.feat);
+    prof_end(c, r, VI_K_OTHER, level, nS);
+    VI_TRY(launched("features"));
+  }
+  r = prof_begin(c, VI_K_INIT);
+  vi::launch_s0(c->st, d, A, red);
   A.evals = ev_pass;
   prof_end(c, r, VI_K_INIT, level, nS);
   VI_TRY(launched("s0"));
@@ -298,7 +318,7 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
       // previous pass at the same stride
       A.t = ++t;
       A.since = (c->prm.n_jf > 0 && t > np) ? t - np : 0;
-      vi::launch_pass(c->st, d, A);
+      vi::launch_pass(c->st, d, A, red);
       pass_units += (int64_t)nS;
       ++n_pass;
       VI_TRY(launched("pass"));
@@ -314,6 +334,13 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
     vi::launch_copy_targets(c->st, tlist, nS, d.nnf1, d.nnf0);
     prof_end(c, r, VI_K_OTHER, level, nS);
     VI_TRY(launched("copy"));
+  }
+  if (red) {
+    // the reconstruction weighs the matches by their exact distances
+    r = prof_begin(c, VI_K_OTHER);
+    vi::launch_rerank(c->st, d, tlist, nS);
+    prof_end(c, r, VI_K_OTHER, level, nS);
+    VI_TRY(launched("rerank"));
   }
   return VI_OK;
 }
@@ -566,6 +593,64 @@ vi_status noalloc_scratch(int dev, unsigned char** out) {
 
 }  // namespace
 
+namespace {
+
+// device work space for the PCA of a level, released when it goes out of
+// scope (after the caller's synchronisation)
+struct PcaBuf {
+  int dev = 0;
+  void* p = nullptr;
+  vi_status get(int d, size_t bytes) {
+    dev = d;
+    p = vi::pool_alloc(dev, bytes);
+    return p ? VI_OK : fail(VI_E_NOMEM, "device allocation of the PCA work space failed");
+  }
+  ~PcaBuf() {
+    if (p) vi::pool_free(dev, p);
+  }
+};
+
+// Installs the basis already in lv.redQt (n features, dp columns) and
+// computes the features of every voxel of the level on the current video.
+vi_status install_reduction(vi_ctx* c, int32_t level, int32_t n) {
+  Level& lv = c->lv[level];
+  const int32_t dp = (n + 3) & ~3;
+  if (lv.feat && lv.d.rd != dp) {
+    dfree(c, lv.feat);
+    lv.feat = nullptr;
+  }
+  if (!lv.feat) VI_TRY(dalloc(c, &lv.feat, (size_t)lv.d.V * dp));
+  lv.d.feat = lv.feat;
+  lv.d.rd = dp;
+  lv.red_n = n;
+  vi::launch_features(c->st, lv.d, lv.redQt, patch_dim(c->prm), dp, nullptr, lv.d.V, lv.feat);
+  return launched("features");
+}
+
+// The PCA basis of a level's source patches (d features, n_max samples,
+// iters steps) into lv.redQt; Q (host [d][dim]) and var (host [d]) optional.
+vi_status level_pca(vi_ctx* c, int32_t level, int32_t d, int32_t n_max, int32_t iters,
+                    int16_t* Q, double* var) {
+  Level& lv = c->lv[level];
+  const int32_t dim = patch_dim(c->prm);
+  if (!lv.redQt) VI_TRY(dalloc(c, &lv.redQt, (size_t)dim * vi::kMaxRed));
+  PcaBuf work, qbuf;
+  VI_TRY(work.get(c->dev, vi::pca_work_bytes(dim, n_max)));
+  VI_TRY(qbuf.get(c->dev, sizeof(int16_t) * (size_t)dim * vi::kMaxRed));
+  double* rq = nullptr;
+  const vi_status st =
+      vi::pca_basis(c->st, lv.d, dim, d, n_max, iters, std::sqrt((double)c->prm.lambda),
+                    work.p, static_cast<int16_t*>(qbuf.p), lv.redQt, &rq);
+  if (st != VI_OK) return fail(st, "PCA launch failed");
+  if (Q)
+    VI_HIP(hipMemcpyAsync(Q, qbuf.p, sizeof(int16_t) * (size_t)d * dim, hipMemcpyDeviceToHost,
+                          c->st));
+  if (var) VI_HIP(hipMemcpyAsync(var, rq, sizeof(double) * d, hipMemcpyDeviceToHost, c->st));
+  return sync(c);
+}
+
+}  // namespace
+
 extern "C" {
 
 vi_status vi_params_default(vi_params* o) {
@@ -586,6 +671,7 @@ vi_status vi_params_default(vi_params* o) {
   o->recon_mode = VI_RECON_WEIGHTED;
   o->seed = 0;
   o->temporal_subsample = 0;
+  o->reduce_dims = 0;
   return VI_OK;
 }
 
@@ -605,6 +691,10 @@ size_t vi_footprint_bytes(const vi_params* prm, int32_t W, int32_t H, int32_t T,
     // target and hole lists: the dilated hole is at most 125x the hole
     const double fr = hole_fraction * 125.0 < 1.0 ? hole_fraction * 125.0 : 1.0;
     total += (size_t)((double)V * (fr + hole_fraction) * 4.0) + 4096;
+    // reduced patch space: features and basis
+    if (prm->reduce_dims > 0)
+      total += (size_t)V * 4 * (size_t)((prm->reduce_dims + 3) & ~3) + 2 * vi::kPatchDimMax *
+                                                                          vi::kMaxRed;
     w = (w + 1) / 2;
     h = (h + 1) / 2;
     t = coarser_T(prm, (int32_t)t);
@@ -612,6 +702,7 @@ size_t vi_footprint_bytes(const vi_params* prm, int32_t W, int32_t H, int32_t T,
   // creation temporaries at the finest level: gradients 4, box sums 8,
   // dilation scratch 2, compaction list 4
   total += (size_t)V0 * 18;
+  if (prm->reduce_dims > 0) total += vi::pca_work_bytes(patch_dim(*prm), 65536);
   return total + (size_t)(64u << 20);
 }
 
@@ -718,6 +809,12 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
   dfree(c, t1);
   dfree(c, t2);
   dfree(c, tmp_list);
+  // the reduced patch space of every level: PCA of its own sources
+  for (int l = 0; l < c->L && prm->reduce_dims > 0; ++l) {
+    if ((st = level_pca(c, l, prm->reduce_dims, 65536, 64, nullptr, nullptr))) return bail(st);
+    if ((st = install_reduction(c, l, prm->reduce_dims))) return bail(st);
+  }
+  if (prm->reduce_dims > 0 && (st = sync(c))) return bail(st);
   *out = c;
   return VI_OK;
 }
@@ -952,6 +1049,92 @@ vi_status vi_closer_than_constant(const uint8_t* ref, int32_t n_ref, const uint8
       ref, n_ref, vol, W, H, T, pw, ph, pt, mu, reinterpret_cast<unsigned long long*>(counts),
       static_cast<hipStream_t>(hip_stream));
   return st == VI_OK ? VI_OK : fail(st, "vi_closer_than_constant: launch failed");
+}
+
+vi_status vi_pca_moments(vi_ctx* c, int32_t level, int32_t n_max, uint64_t* S1, uint64_t* S2,
+                         int64_t* n) {
+  VI_TRY(level_ok(c, level));
+  if (!S1 || !S2 || !n) return fail(VI_E_INVAL, "null output");
+  if (n_max < 1 || n_max > (1 << 20)) return fail(VI_E_INVAL, "n_max must be in [1, 2^20]");
+  const int32_t dim = patch_dim(c->prm);
+  PcaBuf work;
+  VI_TRY(work.get(c->dev, vi::pca_work_bytes(dim, n_max)));
+  unsigned long long *d1 = nullptr, *d2 = nullptr;
+  *n = vi::pca_moments(c->st, c->lv[level].d, dim, n_max, work.p, &d1, &d2);
+  VI_TRY(launched("moments"));
+  VI_HIP(hipMemcpyAsync(S1, d1, sizeof(uint64_t) * dim, hipMemcpyDeviceToHost, c->st));
+  VI_HIP(hipMemcpyAsync(S2, d2, sizeof(uint64_t) * (size_t)dim * dim, hipMemcpyDeviceToHost,
+                        c->st));
+  return sync(c);
+}
+
+vi_status vi_pca_basis(vi_ctx* c, int32_t level, int32_t d, int32_t n_max, int32_t iters,
+                       int16_t* Q, double* variance) {
+  VI_TRY(level_ok(c, level));
+  if (!Q) return fail(VI_E_INVAL, "null output");
+  if (d < 1 || d > vi::kMaxRed) return fail(VI_E_INVAL, "d must be in [1, 32]");
+  if (n_max < 1 || n_max > (1 << 20)) return fail(VI_E_INVAL, "n_max must be in [1, 2^20]");
+  if (iters < 0 || iters > 10000) return fail(VI_E_INVAL, "iters must be in [0, 10000]");
+  if (c->batch) return fail(VI_E_STATE, "the clip is in a batch");
+  // the level's basis buffer is reused: keep a basis in use intact
+  Level& lv = c->lv[level];
+  int16_t* keep = nullptr;
+  if (lv.d.rd > 0) std::swap(keep, lv.redQt);
+  const vi_status st = level_pca(c, level, d, n_max, iters, Q, variance);
+  if (keep) {
+    dfree(c, lv.redQt);
+    lv.redQt = keep;
+  }
+  return st;
+}
+
+vi_status vi_set_reduction(vi_ctx* c, int32_t level, const int16_t* Q, int32_t d) {
+  VI_TRY(level_ok(c, level));
+  if (c->batch) return fail(VI_E_STATE, "the clip is in a batch");
+  if (d < 0 || d > vi::kMaxRed) return fail(VI_E_INVAL, "d must be in [0, 32]");
+  Level& lv = c->lv[level];
+  if (d == 0) {
+    VI_TRY(sync(c));
+    dfree(c, lv.feat);
+    lv.feat = nullptr;
+    lv.d.feat = nullptr;
+    lv.d.rd = 0;
+    lv.red_n = 0;
+    return VI_OK;
+  }
+  if (!Q) return fail(VI_E_INVAL, "null basis");
+  const int32_t dim = patch_dim(c->prm);
+  const int32_t dp = (d + 3) & ~3;
+  // every feature's sum must stay inside int32: sum |Q| * 255 + 128 < 2^31
+  std::vector<int16_t> qt((size_t)dim * vi::kMaxRed, 0);
+  for (int k = 0; k < d; ++k) {
+    int64_t a = 0;
+    for (int i = 0; i < dim; ++i) {
+      const int16_t v = Q[(size_t)k * dim + i];
+      a += v < 0 ? -(int64_t)v : (int64_t)v;
+      qt[(size_t)i * dp + k] = v;
+    }
+    if (a * 255 + 128 >= (int64_t(1) << 31))
+      return fail(VI_E_INVAL, "a basis row whose feature sums could overflow 32 bits");
+  }
+  if (!lv.redQt) VI_TRY(dalloc(c, &lv.redQt, (size_t)dim * vi::kMaxRed));
+  VI_TRY(sync(c));  // no queued search reads the old basis any more
+  VI_HIP(hipMemcpyAsync(lv.redQt, qt.data(), sizeof(int16_t) * (size_t)dim * dp,
+                        hipMemcpyHostToDevice, c->st));
+  VI_TRY(install_reduction(c, level, d));
+  return sync(c);
+}
+
+vi_status vi_features(const vi_ctx* c, int32_t level, int32_t d, int32_t* out) {
+  VI_TRY(level_ok(c, level));
+  if (!out) return fail(VI_E_INVAL, "null output");
+  const Level& lv = c->lv[level];
+  if (lv.d.rd == 0) return fail(VI_E_STATE, "the level has no reduced patch space");
+  if (d != lv.red_n) return fail(VI_E_INVAL, "d is not the level's feature count");
+  VI_HIP(hipMemcpy2DAsync(out, sizeof(int32_t) * lv.red_n, lv.feat, sizeof(int32_t) * lv.d.rd,
+                          sizeof(int32_t) * lv.red_n, (size_t)lv.d.V, hipMemcpyDeviceToDevice,
+                          c->st));
+  return VI_OK;
 }
 
 vi_status vi_transition(vi_ctx* c, int32_t level) {
@@ -1549,6 +1732,9 @@ vi_status vi_batch_add(vi_batch* b, vi_ctx* c) {
     return fail(VI_E_INVAL, "all clips of a batch share pm_iters and jf_steps");
   if ((int32_t)b->members.size() >= b->cap_jobs) return fail(VI_E_BUDGET, "the batch is full");
   if (c->phase == 2) return fail(VI_E_STATE, "the clip has already finished");
+  for (int l = 0; l < c->L; ++l)
+    if (c->lv[l].d.rd > 0)
+      return fail(VI_E_INVAL, "clips searched with the reduced distance run alone");
   if (!b->have_sched) {
     b->sched = c->prm;
     b->have_sched = true;

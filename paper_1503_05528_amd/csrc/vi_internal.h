@@ -73,7 +73,14 @@ struct DevLevel {
                    // (5x5x1 patches of single images, T = 1)
   int32_t lambda;
   uint64_t seed;
+  // dimensionality-reduced patch space: rd features per voxel (a multiple of
+  // four; 0 = the exact distance) in feat [V][rd]
+  const int32_t* feat;
+  int32_t rd;
 };
+
+constexpr int kPatchDimMax = 625;  // coordinates of a 5x5x5 patch vector (5 channels)
+constexpr int kMaxRed = 32;        // features of the reduced patch space, at most
 
 // One synchronous pass of the search over a target list.
 struct PassArgs {
@@ -156,8 +163,11 @@ void launch_sources(hipStream_t st, DevLevel L);
 void launch_fill_nnf(hipStream_t st, int2* nnf, uint8_t* nvox, int32_t V);
 void launch_fill_u64(hipStream_t st, unsigned long long* p, int32_t n);
 
-void launch_s0(hipStream_t st, DevLevel L, const PassArgs& A);
-void launch_pass(hipStream_t st, DevLevel L, const PassArgs& A);
+// red: compare the reduced distance (unmasked searches of a level with
+// features); launch_rerank then evaluates every target's match exactly
+void launch_s0(hipStream_t st, DevLevel L, const PassArgs& A, bool red = false);
+void launch_pass(hipStream_t st, DevLevel L, const PassArgs& A, bool red = false);
+void launch_rerank(hipStream_t st, DevLevel L, const int32_t* tlist, int32_t nS);
 void launch_copy_targets(hipStream_t st, const int32_t* tlist, int32_t nS, const int2* src,
                          int2* dst);
 
@@ -229,6 +239,24 @@ vi_status align_unwarp(const uint8_t* aligned, const uint8_t* rgb, const uint8_t
 vi_status closer_than_constant(const uint8_t* ref, int32_t n_ref, const uint8_t* vol, int32_t W,
                                int32_t H, int32_t T, int32_t pw, int32_t ph, int32_t pt,
                                int32_t mu, unsigned long long* counts, hipStream_t st);
+
+// Dimensionality-reduced patch space (vi_reduce.hip).  Qt [dim][dp] int16
+// (dp = features rounded up to a multiple of 4, zero rows beyond them);
+// features of the voxels of list (all voxels when null) into feat [V][dp].
+void launch_features(hipStream_t st, const DevLevel& L, const int16_t* Qt, int32_t dim,
+                     int32_t dp, const int32_t* list, int32_t n, int32_t* feat);
+// bytes of device work space the PCA of one level needs
+size_t pca_work_bytes(int32_t dim, int32_t n_max);
+// exact moments of every k-th source's patch vector (k = ceil(nD / n_max));
+// returns the sample count and points S1 [dim], S2 [dim][dim] into work
+int64_t pca_moments(hipStream_t st, const DevLevel& L, int32_t dim, int32_t n_max, void* work,
+                    unsigned long long** S1, unsigned long long** S2);
+// the d leading principal directions of the weighted patch vectors (iters
+// steps of orthogonal iteration), quantised: dQ [d][dim], dQt [dim][dp];
+// rq points into work at the captured variances [dp]
+vi_status pca_basis(hipStream_t st, const DevLevel& L, int32_t dim, int32_t d, int32_t n_max,
+                    int32_t iters, double wtex, void* work, int16_t* dQ, int16_t* dQt,
+                    double** rq);
 
 // stream compaction (stable): out[k] = i for the k-th i with flags[i] != 0
 size_t compact_temp_bytes(int32_t n);

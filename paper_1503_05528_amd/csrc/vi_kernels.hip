@@ -237,6 +237,28 @@ __device__ __forceinline__ uint32_t patch_ssd(const DevLevel& L, const uint8_t* 
   return ssd_groups<false, MASKED, ABORT>(L, excl, p, px, py, pt, c, abort_above, nvox);
 }
 
+// Reduced distance of the dimensionality-reduced patch space: the sum over
+// the level's rd features (a multiple of four, zero padded) of
+// (f(p) - f(c))^2, saturated at 2^31 - 1.  Features are below 2^23 in
+// magnitude, so a difference fits in 32 bits and a square at or above 2^31
+// saturates at once.
+__device__ __forceinline__ uint32_t red_dist(const DevLevel& L, int32_t p, int32_t c) {
+  const int4* a = reinterpret_cast<const int4*>(L.feat + (size_t)p * L.rd);
+  const int4* b = reinterpret_cast<const int4*>(L.feat + (size_t)c * L.rd);
+  uint32_t s = 0;
+  for (int k = 0; k < L.rd / 4; ++k) {
+    const int4 u = a[k], v = b[k];
+    const int32_t e[4] = {u.x - v.x, u.y - v.y, u.z - v.z, u.w - v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t m = (uint32_t)abs(e[j]);
+      const uint32_t sq = m >= 46341u ? 0x7fffffffu : m * m;
+      s = min(s + sq, 0x7fffffffu);
+    }
+  }
+  return s;
+}
+
 // Wave-wide reductions with DPP row operations instead of LDS permutes:
 // adjacent lanes, quads, half rows and rows of 16 by swizzles within a row,
 // then the four rows through row_bcast:15 (rows 1 and 3) and row_bcast:31
@@ -290,7 +312,7 @@ __device__ __forceinline__ void count_evals(unsigned long long* evals, int n) {
 // missing or not a source (Philox purpose 1), then the distance of every
 // target's match on the current video.
 // ------------------------------------------------------------------------
-template <bool MASKED>
+template <bool MASKED, bool RED = false>
 __device__ __forceinline__ int s0_target(const DevLevel& L, const PassArgs& A, int32_t i) {
   if (i >= A.nS) return 0;
   const int32_t p = A.tlist[i];
@@ -305,6 +327,13 @@ __device__ __forceinline__ int s0_target(const DevLevel& L, const PassArgs& A, i
     philox4x64_10((uint64_t)p, A.step, 0, ((uint64_t)L.level << 8) | 1u, L.seed, 0, w);
     c = L.dlist[draw_below(w[0], (uint32_t)L.nD)];
   }
+  if (RED) {
+    // the reduced distance; the exact one (and the count and the marks) is
+    // written after the search
+    nnf[p] = make_int2(c, (int32_t)red_dist(L, p, c));
+    L.chg[p] = 0;
+    return 1;
+  }
   int32_t n;
   const uint32_t d = patch_ssd<MASKED, false>(L, A.excl, p, px, py, pt, c, 0xffffffffu, n);
   nnf[p] = make_int2(c, (int32_t)d);
@@ -314,10 +343,28 @@ __device__ __forceinline__ int s0_target(const DevLevel& L, const PassArgs& A, i
   return 1;
 }
 
-template <bool MASKED>
+template <bool MASKED, bool RED>
 __global__ __launch_bounds__(kBlock) void k_s0(DevLevel L, PassArgs A) {
-  const int ne = s0_target<MASKED>(L, A, blockIdx.x * kBlock + threadIdx.x);
+  const int ne = s0_target<MASKED, RED>(L, A, blockIdx.x * kBlock + threadIdx.x);
   count_evals(A.evals, ne);
+}
+
+// After a search with the reduced distance: every target's match evaluated
+// with the exact patch distance, which the reconstruction weights use; the
+// marks tell the next reconstruction that every target may have changed.
+__global__ __launch_bounds__(kBlock) void k_rerank(DevLevel L, const int32_t* __restrict__ tlist,
+                                                   int32_t nS) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nS) return;
+  const int32_t p = tlist[i];
+  int32_t px, py, pt;
+  unlin(L, p, px, py, pt);
+  const int32_t c = L.nnf0[p].x;
+  int32_t n;
+  const uint32_t d = patch_ssd<false, false>(L, nullptr, p, px, py, pt, c, 0xffffffffu, n);
+  L.nnf0[p] = make_int2(c, (int32_t)d);
+  L.nvox[p] = (uint8_t)n;
+  L.rmark[p] = (uint8_t)L.repoch;
 }
 
 // Block index -> logical block such that the workgroups that land on one XCD
@@ -371,7 +418,7 @@ struct PassShared {
 // One block of BLK consecutive targets (block index blk of the target list);
 // returns the evaluations this thread accounts for.  All threads of the
 // workgroup must call it together.
-template <int BLK, bool MASKED>
+template <int BLK, bool MASKED, bool RED = false>
 __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, int32_t blk,
                                           PassShared<BLK>& sh) {
   int32_t* s_p = sh.p;
@@ -500,8 +547,10 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
       // a candidate whose partial distance exceeds the current best cannot win
       const uint32_t bound = (uint32_t)(s_best[lt] >> 3);
       int32_t n;
-      const uint32_t d = patch_ssd<MASKED, true>(L, A.excl, s_p[lt], xy & 0xFFFF, xy >> 16,
-                                                 s_t[lt], s_cand[lt * 6 + j], bound, n);
+      const uint32_t d =
+          RED ? red_dist(L, s_p[lt], s_cand[lt * 6 + j])
+              : patch_ssd<MASKED, true>(L, A.excl, s_p[lt], xy & 0xFFFF, xy >> 16, s_t[lt],
+                                        s_cand[lt * 6 + j], bound, n);
       if (d <= bound)
         atomicMin(&s_best[lt], ((unsigned long long)d << 3) | (unsigned long long)(j + 1));
     }
@@ -536,7 +585,9 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
       const int nr = (best_d != 0 && rc != best_c) ? 1 : 0;
       if (nr) {
         int32_t n;
-        const uint32_t d = patch_ssd<MASKED, true>(L, A.excl, p, px, py, pt, rc, best_d - 1u, n);
+        const uint32_t d = RED ? red_dist(L, p, rc)
+                               : patch_ssd<MASKED, true>(L, A.excl, p, px, py, pt, rc,
+                                                         best_d - 1u, n);
         if (d < best_d && L.dsrc[rc]) {
           best_d = d;
           best_c = rc;
@@ -556,10 +607,10 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
   return ne;
 }
 
-template <bool MASKED>
+template <bool MASKED, bool RED>
 __global__ __launch_bounds__(kBlock) void k_pass(DevLevel L, PassArgs A) {
   __shared__ PassShared<kBlock> sh;
-  const int ne = pass_block<kBlock, MASKED>(L, A, xcd_block(blockIdx.x, gridDim.x), sh);
+  const int ne = pass_block<kBlock, MASKED, RED>(L, A, xcd_block(blockIdx.x, gridDim.x), sh);
   count_evals(A.evals, ne);
 }
 
@@ -1423,20 +1474,29 @@ void launch_fill_u64(hipStream_t st, unsigned long long* p, int32_t n) {
   k_fill_u64<<<grid_for(n), kBlock, 0, st>>>(p, n);
 }
 
-void launch_s0(hipStream_t st, DevLevel L, const PassArgs& A) {
+void launch_s0(hipStream_t st, DevLevel L, const PassArgs& A, bool red) {
   if (A.nS <= 0) return;
   if (A.excl)
-    k_s0<true><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
+    k_s0<true, false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
+  else if (red)
+    k_s0<false, true><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
   else
-    k_s0<false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
+    k_s0<false, false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
 }
 
-void launch_pass(hipStream_t st, DevLevel L, const PassArgs& A) {
+void launch_pass(hipStream_t st, DevLevel L, const PassArgs& A, bool red) {
   if (A.nS <= 0) return;
   if (A.excl)
-    k_pass<true><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
+    k_pass<true, false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
+  else if (red)
+    k_pass<false, true><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
   else
-    k_pass<false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
+    k_pass<false, false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
+}
+
+void launch_rerank(hipStream_t st, DevLevel L, const int32_t* tlist, int32_t nS) {
+  if (nS <= 0) return;
+  k_rerank<<<grid_for(nS), kBlock, 0, st>>>(L, tlist, nS);
 }
 
 void launch_copy_targets(hipStream_t st, const int32_t* tlist, int32_t nS, const int2* src,

@@ -36,6 +36,7 @@ class Params(C.Structure):
         ("recon_mode", C.c_int32),
         ("seed", C.c_uint64),
         ("temporal_subsample", C.c_int32),
+        ("reduce_dims", C.c_int32),
     ]
 
 
@@ -60,6 +61,11 @@ SIGNATURES = {
     "vi_align_compose": (_i32, [_f64p, _i32, _f64p]),
     "vi_align_warp": (_i32, [_vp, _vp, _i32, _i32, _i32, _f64p, _vp, _vp, _vp]),
     "vi_align_unwarp": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _f64p, _vp, _vp]),
+    "vi_set_reduction": (_i32, [_vp, _i32, C.POINTER(C.c_int16), _i32]),
+    "vi_features": (_i32, [_vp, _i32, _i32, _vp]),
+    "vi_pca_moments": (_i32, [_vp, _i32, _i32, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                              C.POINTER(_i64)]),
+    "vi_pca_basis": (_i32, [_vp, _i32, _i32, _i32, _i32, C.POINTER(C.c_int16), _f64p]),
     "vi_closer_than_constant": (_i32, [_vp, _i32, _vp, _i32, _i32, _i32, _i32, _i32, _i32,
                                        _i32, _vp, _vp]),
     "vi_params_default": (_i32, [C.c_void_p]),
@@ -312,6 +318,53 @@ class Clip:
 
     def transition(self, level):
         _check("vi_transition", lib().vi_transition(self.h, level))
+
+    # ------------------------------------------- reduced patch space (Sec. 5)
+    @property
+    def patch_dim(self):
+        return 5 * self.params.patch[0] * self.params.patch[1] * self.params.patch[2]
+
+    def pca_moments(self, level, n_max=65536):
+        """(S1 [dim], S2 [dim][dim], n): exact moments of the sampled source
+        patch vectors (host arrays)."""
+        import numpy as np
+        dim = self.patch_dim
+        S1 = np.zeros(dim, np.uint64)
+        S2 = np.zeros((dim, dim), np.uint64)
+        n = C.c_int64(0)
+        _check("vi_pca_moments", lib().vi_pca_moments(
+            self.h, level, n_max, S1.ctypes.data_as(C.POINTER(C.c_uint64)),
+            S2.ctypes.data_as(C.POINTER(C.c_uint64)), C.byref(n)))
+        return S1, S2, int(n.value)
+
+    def pca_basis(self, level, d, n_max=65536, iters=64):
+        """(Q [d][dim] int16, captured variance [d]) of the level's source
+        patches, computed on the GPU."""
+        import numpy as np
+        Q = np.zeros((d, self.patch_dim), np.int16)
+        var = np.zeros(d, np.float64)
+        _check("vi_pca_basis", lib().vi_pca_basis(
+            self.h, level, d, n_max, iters, Q.ctypes.data_as(C.POINTER(C.c_int16)),
+            var.ctypes.data_as(_f64p)))
+        return Q, var
+
+    def set_reduction(self, level, Q):
+        """The level's searches compare the features of basis Q [d][dim]
+        (host int16 array; None: the exact distance again)."""
+        import numpy as np
+        if Q is None:
+            _check("vi_set_reduction", lib().vi_set_reduction(self.h, level, None, 0))
+            return
+        q = np.ascontiguousarray(Q, np.int16)
+        _check("vi_set_reduction", lib().vi_set_reduction(
+            self.h, level, q.ctypes.data_as(C.POINTER(C.c_int16)), q.shape[0]))
+
+    def features(self, level, d):
+        """The level's voxel features, device int32 [T][H][W][d]."""
+        W, H, T = self.dims(level)
+        out = self._new((T, H, W, d), torch.int32)
+        _check("vi_features", lib().vi_features(self.h, level, d, _ptr(out)))
+        return out
 
     def inpaint(self, out: torch.Tensor | None = None):
         if out is None:
