@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--config", default="hd", choices=["sd", "hd", "tiny"])
     ap.add_argument("--no-realign", action="store_true",
                     help="skip the realignment measurement (Sec. 3.4)")
+    ap.add_argument("--no-reduced", action="store_true",
+                    help="skip the PCA-reduced patch space measurement (Sec. 5)")
+    ap.add_argument("--no-image", action="store_true",
+                    help="skip the 2-D image inpainting measurement")
     ap.add_argument("--no-appb", action="store_true",
                     help="skip the textured-patch experiment (App. B)")
     ap.add_argument("--no-sd", action="store_true",
@@ -492,6 +496,41 @@ def measure_realign(steps=3):
             "warp_call_frac_of_hbm_peak": warp_bytes / warp / 1e9 / HBM_PEAK_GBS}
 
 
+def measure_image(steps=3, em_iters=20):
+    """2-D image inpainting with 5x5x1 patches (T = 1) on the same kernels:
+    whole inpaintings of a 1920x1080 and a 3840x2160 still image from
+    inputs resident in HBM (the hole about 5 % of the pixels)."""
+    import torch
+    from paper_1503_05528_amd import synth, vi
+    res = []
+    for W, H, levels in ((1920, 1080, 5), (3840, 2160, 6)):
+        img = synth.image(31, W, H, frac=0.05, levels=levels)
+        video = torch.from_numpy(img.occluded_input()).cuda()
+        mask = torch.from_numpy(img.mask).cuda()
+        params = vi.default_params(levels=levels, em_tol=-1.0, em_max_iters=em_iters, seed=1,
+                                   patch=(5, 5, 1))
+
+        def one():
+            g = vi.Clip(video, mask, params=params)
+            g.inpaint()
+            c = g.counters()
+            g.close()
+            return c
+        one()
+        torch.cuda.synchronize()
+        lat, nominal = [], 0
+        for _ in range(steps):
+            s0 = time.perf_counter()
+            nominal += one()["nominal_evals"]
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - s0)
+        res.append({"image": f"{W}x{H}", "levels": levels,
+                    "hole_fraction": float(img.mask.mean()),
+                    "ms_per_image": 1000 * statistics.median(lat),
+                    "nominal_evals_per_s": nominal / sum(lat)})
+    return {"workload": "still images, 5x5x1 patches, 20 EM iterations per level", "rows": res}
+
+
 def realign_cpu_baseline():
     """CPU baseline leg of the realignment: the oracle's estimation and warp
     of the same clip on all host cores."""
@@ -773,10 +812,11 @@ def roofline_of(workload, pass_evals, pass_units, pass_ms, pass_launches, nomina
     }
 
 
-def measure_plain(config, steps, warmup, em_iters, temporal=False):
+def measure_plain(config, steps, warmup, em_iters, temporal=False, reduce_dims=0):
     """Whole inpaintings of one clip from inputs resident in HBM: timed
     steps, per-kind kernel time of one more step, and the roofline record
-    (temporal: pyramids subsampled in time as well)."""
+    (temporal: pyramids subsampled in time as well; reduce_dims: searches
+    in the PCA-reduced patch space)."""
     import torch
     from paper_1503_05528_amd import vi
     clip, levels = make_clip(config)
@@ -784,14 +824,20 @@ def measure_plain(config, steps, warmup, em_iters, temporal=False):
     video = torch.from_numpy(clip.occluded_input()).cuda()
     mask = torch.from_numpy(clip.mask).cuda()
     params = vi.default_params(levels=levels, em_tol=-1.0, em_max_iters=em_iters, seed=1,
-                               temporal_subsample=1 if temporal else 0)
+                               temporal_subsample=1 if temporal else 0,
+                               reduce_dims=reduce_dims)
     torch.cuda.synchronize()
 
+    last = {}
+
     def one_step(profile=None):
+        c0 = time.perf_counter()
         g = vi.Clip(video, mask, params=params)
+        last["create_s"] = time.perf_counter() - c0
         if profile:
             g.profile(True, kinds=profile)
         out = g.inpaint()
+        last["out"] = out
         rec = g.profile_read() if profile else []
         cnt = g.counters()
         g.close()
@@ -839,12 +885,19 @@ def measure_plain(config, steps, warmup, em_iters, temporal=False):
     pas = kinds.get("pass", {"launches": 1, "units": 0, "ms": 1.0, "targets_per_search": 0})
     roof = roofline_of(config, pass_evals, pas["units"], pas["ms"], pas["launches"], nominal,
                        pas["targets_per_search"])
+    # mean |error| over the hole's colour channels against the clip's true video
+    hole = torch.from_numpy(clip.mask).cuda().bool()
+    err = (last["out"][hole].float() - torch.from_numpy(clip.video).cuda()[hole].float())
+    hole_err = float(err.abs().mean())
     return {
         "value": nominal / elapsed, "ms_per_step": 1000.0 * elapsed / steps,
         "clips_per_s": steps / elapsed, "steps": steps, "warmup": warmup,
         "workload": f"{config} plain run {W}x{H}x{T}, {levels}-level pyramid"
-                    f"{' subsampled in time as well' if temporal else ''}, 5x5x5 patches, "
-                    f"{em_iters} EM iterations per level, one clip per step",
+                    f"{' subsampled in time as well' if temporal else ''}, 5x5x5 patches"
+                    f"{f' compared in a {reduce_dims}-dimensional PCA space' if reduce_dims else ''}"
+                    f", {em_iters} EM iterations per level, one clip per step",
+        "hole_mean_abs_error": hole_err,
+        "create_ms": 1000 * last["create_s"],
         "latency_p50_ms": 1000 * percentile(lat, 0.5),
         "latency_p99_ms": 1000 * percentile(lat, 0.99),
         "latency_samples": len(lat),
@@ -916,6 +969,7 @@ def main():
         "latency_p99_ms": m["latency_p99_ms"],
         "latency_samples": m["latency_samples"],
         "effective_evals_per_s": m["effective_evals_per_s"],
+        "hole_mean_abs_error": m["hole_mean_abs_error"],
         "kernel_ms_per_step": m["kernel_ms_per_step"],
         "kernel_ms_per_step_by_level": m["kernel_ms_per_step_by_level"],
         "roofline": m["roofline"],
@@ -943,6 +997,17 @@ def main():
     if not a.no_realign:
         log("realignment: shaking-camera clip")
         line["realign"] = measure_realign()
+    if not a.no_reduced:
+        # the reduced patch space (Sec. 5) on the headline clip
+        r = measure_plain(a.config, 2, 1, a.em_iters, reduce_dims=16)
+        r.pop("clip")
+        line["reduced"] = {k: r[k] for k in ("workload", "value", "ms_per_step", "create_ms",
+                                             "kernel_ms_per_step", "hole_mean_abs_error")}
+        line["reduced"]["exact_hole_mean_abs_error"] = m["hole_mean_abs_error"]
+        line["reduced"]["exact_ms_per_step"] = m["ms_per_step"]
+    if not a.no_image:
+        log("images: 5x5x1 patches")
+        line["image"] = measure_image()
     if not a.no_appb:
         log("App. B: random patches against the constant patch")
         line["appb"] = measure_appb()

@@ -82,7 +82,7 @@ typedef struct {
                            Sec. 5 proposes as an acceleration: at creation
                            every level gets the reduce_dims leading principal
                            directions of its source patches (65536 sampled
-                           sources, 64 steps of orthogonal iteration; see
+                           sources, 32 steps of orthogonal iteration; see
                            vi_pca_basis), and the searches of the EM loop
                            compare those features (vi_set_reduction) */
 } vi_params;
@@ -380,7 +380,8 @@ vi_status vi_pca_moments(vi_ctx* ctx, int32_t level, int32_t n_max, uint64_t* S1
  * covariance C_ij = (w_i w_j)(S2_ij / n - (S1_i / n)(S1_j / n)) of the
  * weighted vectors in double precision, then `iters` steps of orthogonal
  * iteration (d columns rounded up to a multiple of 4, fixed pseudo-random
- * start, classical Gram-Schmidt applied twice), and Q[k][i] =
+ * start, orthonormalised by classical Gram-Schmidt applied twice after
+ * every fourth product and after the last), and Q[k][i] =
  * rint(256 w_i b_ik) for the first d columns.  Q (host) [d][dim];
  * variance (host) [d] or NULL: b_k' C b_k, the variance each direction
  * captures.  Does not change the level's reduction.  Syncs.

@@ -52,10 +52,12 @@ struct Level {
   // the reconstruction marks) changed the state: the next one may skip
   bool recon_ok = false;
   int32_t recon_last = -1;
-  // dimensionality-reduced patch space: basis (transposed, [dim][kMaxRed]
-  // int16), features [V][d.rd], number of features in use
-  int16_t* redQt = nullptr;
+  // dimensionality-reduced patch space: basis in the feature kernel's layout
+  // ([rows][kPairs][d.rd] int32), features [V][d.rd], entries before a
+  // search, number of features in use
+  int32_t* redQp = nullptr;
   int32_t* feat = nullptr;
+  int2* prev = nullptr;
   int32_t red_n = 0;
 };
 
@@ -286,7 +288,7 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
   int r;
   if (red) {
     r = prof_begin(c, VI_K_OTHER);
-    vi::launch_features(c->st, d, lv.redQt, patch_dim(c->prm), d.rd, tlist, nS, lv.feat);
+    vi::launch_features(c->st, d, lv.redQp, patch_dim(c->prm), d.rd, tlist, nS, lv.feat);
     prof_end(c, r, VI_K_OTHER, level, nS);
     VI_TRY(launched("features"));
   }
@@ -610,7 +612,7 @@ struct PcaBuf {
   }
 };
 
-// Installs the basis already in lv.redQt (n features, dp columns) and
+// Installs the basis already in lv.redQp (n features, dp columns) and
 // computes the features of every voxel of the level on the current video.
 vi_status install_reduction(vi_ctx* c, int32_t level, int32_t n) {
   Level& lv = c->lv[level];
@@ -620,27 +622,29 @@ vi_status install_reduction(vi_ctx* c, int32_t level, int32_t n) {
     lv.feat = nullptr;
   }
   if (!lv.feat) VI_TRY(dalloc(c, &lv.feat, (size_t)lv.d.V * dp));
+  if (!lv.prev) VI_TRY(dalloc(c, &lv.prev, (size_t)lv.d.V));
   lv.d.feat = lv.feat;
+  lv.d.prev = lv.prev;
   lv.d.rd = dp;
   lv.red_n = n;
-  vi::launch_features(c->st, lv.d, lv.redQt, patch_dim(c->prm), dp, nullptr, lv.d.V, lv.feat);
+  vi::launch_features(c->st, lv.d, lv.redQp, patch_dim(c->prm), dp, nullptr, lv.d.V, lv.feat);
   return launched("features");
 }
 
 // The PCA basis of a level's source patches (d features, n_max samples,
-// iters steps) into lv.redQt; Q (host [d][dim]) and var (host [d]) optional.
+// iters steps) into lv.redQp; Q (host [d][dim]) and var (host [d]) optional.
 vi_status level_pca(vi_ctx* c, int32_t level, int32_t d, int32_t n_max, int32_t iters,
                     int16_t* Q, double* var) {
   Level& lv = c->lv[level];
   const int32_t dim = patch_dim(c->prm);
-  if (!lv.redQt) VI_TRY(dalloc(c, &lv.redQt, (size_t)dim * vi::kMaxRed));
+  if (!lv.redQp) VI_TRY(dalloc(c, &lv.redQp, (size_t)(dim / 25) * vi::kPairs * vi::kMaxRed));
   PcaBuf work, qbuf;
   VI_TRY(work.get(c->dev, vi::pca_work_bytes(dim, n_max)));
   VI_TRY(qbuf.get(c->dev, sizeof(int16_t) * (size_t)dim * vi::kMaxRed));
   double* rq = nullptr;
   const vi_status st =
       vi::pca_basis(c->st, lv.d, dim, d, n_max, iters, std::sqrt((double)c->prm.lambda),
-                    work.p, static_cast<int16_t*>(qbuf.p), lv.redQt, &rq);
+                    work.p, static_cast<int16_t*>(qbuf.p), lv.redQp, &rq);
   if (st != VI_OK) return fail(st, "PCA launch failed");
   if (Q)
     VI_HIP(hipMemcpyAsync(Q, qbuf.p, sizeof(int16_t) * (size_t)d * dim, hipMemcpyDeviceToHost,
@@ -693,8 +697,8 @@ size_t vi_footprint_bytes(const vi_params* prm, int32_t W, int32_t H, int32_t T,
     total += (size_t)((double)V * (fr + hole_fraction) * 4.0) + 4096;
     // reduced patch space: features and basis
     if (prm->reduce_dims > 0)
-      total += (size_t)V * 4 * (size_t)((prm->reduce_dims + 3) & ~3) + 2 * vi::kPatchDimMax *
-                                                                          vi::kMaxRed;
+      total += (size_t)V * (4 * (size_t)((prm->reduce_dims + 3) & ~3) + 8) +
+               2 * vi::kPatchDimMax * vi::kMaxRed;
     w = (w + 1) / 2;
     h = (h + 1) / 2;
     t = coarser_T(prm, (int32_t)t);
@@ -811,7 +815,7 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
   dfree(c, tmp_list);
   // the reduced patch space of every level: PCA of its own sources
   for (int l = 0; l < c->L && prm->reduce_dims > 0; ++l) {
-    if ((st = level_pca(c, l, prm->reduce_dims, 65536, 64, nullptr, nullptr))) return bail(st);
+    if ((st = level_pca(c, l, prm->reduce_dims, 65536, 32, nullptr, nullptr))) return bail(st);
     if ((st = install_reduction(c, l, prm->reduce_dims))) return bail(st);
   }
   if (prm->reduce_dims > 0 && (st = sync(c))) return bail(st);
@@ -1078,12 +1082,12 @@ vi_status vi_pca_basis(vi_ctx* c, int32_t level, int32_t d, int32_t n_max, int32
   if (c->batch) return fail(VI_E_STATE, "the clip is in a batch");
   // the level's basis buffer is reused: keep a basis in use intact
   Level& lv = c->lv[level];
-  int16_t* keep = nullptr;
-  if (lv.d.rd > 0) std::swap(keep, lv.redQt);
+  int32_t* keep = nullptr;
+  if (lv.d.rd > 0) std::swap(keep, lv.redQp);
   const vi_status st = level_pca(c, level, d, n_max, iters, Q, variance);
   if (keep) {
-    dfree(c, lv.redQt);
-    lv.redQt = keep;
+    dfree(c, lv.redQp);
+    lv.redQp = keep;
   }
   return st;
 }
@@ -1096,8 +1100,11 @@ vi_status vi_set_reduction(vi_ctx* c, int32_t level, const int16_t* Q, int32_t d
   if (d == 0) {
     VI_TRY(sync(c));
     dfree(c, lv.feat);
+    dfree(c, lv.prev);
     lv.feat = nullptr;
+    lv.prev = nullptr;
     lv.d.feat = nullptr;
+    lv.d.prev = nullptr;
     lv.d.rd = 0;
     lv.red_n = 0;
     return VI_OK;
@@ -1105,22 +1112,25 @@ vi_status vi_set_reduction(vi_ctx* c, int32_t level, const int16_t* Q, int32_t d
   if (!Q) return fail(VI_E_INVAL, "null basis");
   const int32_t dim = patch_dim(c->prm);
   const int32_t dp = (d + 3) & ~3;
-  // every feature's sum must stay inside int32: sum |Q| * 255 + 128 < 2^31
-  std::vector<int16_t> qt((size_t)dim * vi::kMaxRed, 0);
+  // every feature's sum must stay inside int32: sum |Q| * 255 + 128 < 2^31;
+  // the device layout pairs the coordinates of each patch row
+  const int32_t rows = dim / 25;
+  std::vector<uint32_t> qp((size_t)rows * vi::kPairs * dp, 0u);
   for (int k = 0; k < d; ++k) {
     int64_t a = 0;
     for (int i = 0; i < dim; ++i) {
       const int16_t v = Q[(size_t)k * dim + i];
       a += v < 0 ? -(int64_t)v : (int64_t)v;
-      qt[(size_t)i * dp + k] = v;
+      const int row = i / 25, cc = i % 25;
+      qp[((size_t)row * vi::kPairs + cc / 2) * dp + k] |= (uint32_t)(uint16_t)v << (16 * (cc & 1));
     }
     if (a * 255 + 128 >= (int64_t(1) << 31))
       return fail(VI_E_INVAL, "a basis row whose feature sums could overflow 32 bits");
   }
-  if (!lv.redQt) VI_TRY(dalloc(c, &lv.redQt, (size_t)dim * vi::kMaxRed));
+  if (!lv.redQp) VI_TRY(dalloc(c, &lv.redQp, (size_t)rows * vi::kPairs * vi::kMaxRed));
   VI_TRY(sync(c));  // no queued search reads the old basis any more
-  VI_HIP(hipMemcpyAsync(lv.redQt, qt.data(), sizeof(int16_t) * (size_t)dim * dp,
-                        hipMemcpyHostToDevice, c->st));
+  VI_HIP(hipMemcpyAsync(lv.redQp, qp.data(), sizeof(uint32_t) * qp.size(), hipMemcpyHostToDevice,
+                        c->st));
   VI_TRY(install_reduction(c, level, d));
   return sync(c);
 }

@@ -77,6 +77,7 @@ struct DevLevel {
   // four; 0 = the exact distance) in feat [V][rd]
   const int32_t* feat;
   int32_t rd;
+  int2* prev;  // [V] a reduced search's targets' entries before it
 };
 
 constexpr int kPatchDimMax = 625;  // coordinates of a 5x5x5 patch vector (5 channels)
@@ -240,10 +241,14 @@ vi_status closer_than_constant(const uint8_t* ref, int32_t n_ref, const uint8_t*
                                int32_t H, int32_t T, int32_t pw, int32_t ph, int32_t pt,
                                int32_t mu, unsigned long long* counts, hipStream_t st);
 
-// Dimensionality-reduced patch space (vi_reduce.hip).  Qt [dim][dp] int16
-// (dp = features rounded up to a multiple of 4, zero rows beyond them);
-// features of the voxels of list (all voxels when null) into feat [V][dp].
-void launch_features(hipStream_t st, const DevLevel& L, const int16_t* Qt, int32_t dim,
+// Dimensionality-reduced patch space (vi_reduce.hip).  A basis on the
+// device: Qp [rows][kPairs][dp] int32 (rows = dim / 25 patch rows (dt, dy);
+// each row's 25 coordinates in 13 pairs, the low 16 bits coordinate 2m,
+// the high 16 bits 2m + 1; dp = features rounded up to a multiple of 4,
+// zero beyond them).  Features of the voxels of list (all voxels when null)
+// into feat [V][dp].
+constexpr int kPairs = 13;
+void launch_features(hipStream_t st, const DevLevel& L, const int32_t* Qp, int32_t dim,
                      int32_t dp, const int32_t* list, int32_t n, int32_t* feat);
 // bytes of device work space the PCA of one level needs
 size_t pca_work_bytes(int32_t dim, int32_t n_max);
@@ -252,10 +257,10 @@ size_t pca_work_bytes(int32_t dim, int32_t n_max);
 int64_t pca_moments(hipStream_t st, const DevLevel& L, int32_t dim, int32_t n_max, void* work,
                     unsigned long long** S1, unsigned long long** S2);
 // the d leading principal directions of the weighted patch vectors (iters
-// steps of orthogonal iteration), quantised: dQ [d][dim], dQt [dim][dp];
-// rq points into work at the captured variances [dp]
+// steps of orthogonal iteration), quantised: dQ [d][dim] and the device
+// layout dQp; rq points into work at the captured variances [dp]
 vi_status pca_basis(hipStream_t st, const DevLevel& L, int32_t dim, int32_t d, int32_t n_max,
-                    int32_t iters, double wtex, void* work, int16_t* dQ, int16_t* dQt,
+                    int32_t iters, double wtex, void* work, int16_t* dQ, int32_t* dQp,
                     double** rq);
 
 // stream compaction (stable): out[k] = i for the k-th i with flags[i] != 0

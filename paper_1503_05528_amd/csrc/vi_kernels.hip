@@ -329,7 +329,8 @@ __device__ __forceinline__ int s0_target(const DevLevel& L, const PassArgs& A, i
   }
   if (RED) {
     // the reduced distance; the exact one (and the count and the marks) is
-    // written after the search
+    // written after the search, which compares it with the entry kept here
+    L.prev[p] = old;
     nnf[p] = make_int2(c, (int32_t)red_dist(L, p, c));
     L.chg[p] = 0;
     return 1;
@@ -350,8 +351,9 @@ __global__ __launch_bounds__(kBlock) void k_s0(DevLevel L, PassArgs A) {
 }
 
 // After a search with the reduced distance: every target's match evaluated
-// with the exact patch distance, which the reconstruction weights use; the
-// marks tell the next reconstruction that every target may have changed.
+// with the exact patch distance, which the reconstruction weights use; a
+// target whose (match, distance, count) differs from before the search is
+// marked for the next reconstruction, as step 0 of an exact search marks.
 __global__ __launch_bounds__(kBlock) void k_rerank(DevLevel L, const int32_t* __restrict__ tlist,
                                                    int32_t nS) {
   const int32_t i = blockIdx.x * kBlock + threadIdx.x;
@@ -362,9 +364,11 @@ __global__ __launch_bounds__(kBlock) void k_rerank(DevLevel L, const int32_t* __
   const int32_t c = L.nnf0[p].x;
   int32_t n;
   const uint32_t d = patch_ssd<false, false>(L, nullptr, p, px, py, pt, c, 0xffffffffu, n);
+  const int2 old = L.prev[p];
+  const uint8_t n_old = L.nvox[p];
   L.nnf0[p] = make_int2(c, (int32_t)d);
   L.nvox[p] = (uint8_t)n;
-  L.rmark[p] = (uint8_t)L.repoch;
+  if (c != old.x || (int32_t)d != old.y || (uint8_t)n != n_old) L.rmark[p] = (uint8_t)L.repoch;
 }
 
 // Block index -> logical block such that the workgroups that land on one XCD
