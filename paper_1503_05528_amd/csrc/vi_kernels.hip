@@ -11,7 +11,6 @@
 // runs on the VALU: the squared difference is expanded as |a|^2 + |b|^2 -
 // 2 a.b with v_dot4_u32_u8 on packed bytes, exact in uint32 arithmetic
 // because every partial sum is a true partial SSD below 2^31.
-#include <hipcub/hipcub.hpp>
 
 #include "vi_internal.h"
 
@@ -1561,18 +1560,121 @@ void launch_out_rgb(hipStream_t st, DevLevel L0, uint8_t* out) {
   k_out_rgb<<<grid_for(L0.V), kBlock, 0, st>>>(L0, out);
 }
 
+// Stable stream compaction: out[k] = i for the k-th i with flags[i] != 0,
+// *d_count = their number.  Three launches over tiles of kCmpTile flags
+// (16 per thread, one 16-byte load): per-tile counts, one workgroup's
+// exclusive scan of the tile counts, then every tile writes its indices in
+// order from its offset (a wave prefix of the per-thread counts by
+// shuffles, the waves' totals through LDS).
+constexpr int kCmpPer = 16;
+constexpr int kCmpTile = kBlock * kCmpPer;
+
+__device__ __forceinline__ uint32_t flags16(const uint8_t* __restrict__ flags, int32_t n,
+                                            int64_t i0, uint32_t bits[1]) {
+  // bit k of the result: flag i0 + k is set
+  uint32_t m = 0;
+  if (i0 + kCmpPer <= n) {
+    const uint4 v = *reinterpret_cast<const uint4*>(flags + i0);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if ((w[q] >> (8 * b)) & 255u) m |= 1u << (4 * q + b);
+  } else {
+    for (int k = 0; k < kCmpPer; ++k)
+      if (i0 + k < n && flags[i0 + k]) m |= 1u << k;
+  }
+  bits[0] = m;
+  return (uint32_t)__popc(m);
+}
+
+__device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* wsum, uint32_t* total) {
+  // inclusive prefix within the wave
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) {
+    before += k < w ? wsum[k] : 0u;
+    all += wsum[k];
+  }
+  *total = all;
+  return before + x - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cmp_count(const uint8_t* __restrict__ flags, int32_t n,
+                                                      uint32_t* __restrict__ tile_count) {
+  __shared__ uint32_t wsum[kBlock / 64];
+  uint32_t bits[1];
+  const int64_t i0 = (int64_t)blockIdx.x * kCmpTile + (int64_t)threadIdx.x * kCmpPer;
+  const uint32_t c = flags16(flags, n, i0, bits);
+  uint32_t total;
+  (void)block_exclusive(c, wsum, &total);
+  if (threadIdx.x == 0) tile_count[blockIdx.x] = total;
+}
+
+// one workgroup: tile_off[t] = sum of tile_count[0..t), *d_count = the total
+__global__ __launch_bounds__(1024) void k_cmp_scan(const uint32_t* __restrict__ tile_count,
+                                                   int32_t nt, uint32_t* __restrict__ tile_off,
+                                                   int32_t* d_count) {
+  __shared__ uint32_t part[1024];
+  const int t = threadIdx.x;
+  const int32_t per = (nt + 1023) / 1024;
+  const int32_t a = t * per, b = min(nt, a + per);
+  uint32_t s = 0;
+  for (int32_t k = a; k < b; ++k) s += tile_count[k];
+  part[t] = s;
+  __syncthreads();
+  // exclusive scan of the 1024 partial sums (Hillis-Steele in LDS)
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint32_t y = t >= o ? part[t - o] : 0u;
+    __syncthreads();
+    part[t] += y;
+    __syncthreads();
+  }
+  uint32_t off = part[t] - s;
+  for (int32_t k = a; k < b; ++k) {
+    tile_off[k] = off;
+    off += tile_count[k];
+  }
+  if (t == 1023) *d_count = (int32_t)part[1023];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cmp_write(const uint8_t* __restrict__ flags, int32_t n,
+                                                      const uint32_t* __restrict__ tile_off,
+                                                      int32_t* __restrict__ out) {
+  __shared__ uint32_t wsum[kBlock / 64];
+  uint32_t bits[1];
+  const int64_t i0 = (int64_t)blockIdx.x * kCmpTile + (int64_t)threadIdx.x * kCmpPer;
+  const uint32_t c = flags16(flags, n, i0, bits);
+  uint32_t total;
+  uint32_t pos = tile_off[blockIdx.x] + block_exclusive(c, wsum, &total);
+  for (uint32_t m = bits[0]; m != 0; m &= m - 1) out[pos++] = (int32_t)(i0 + __ffs(m) - 1);
+}
+
 size_t compact_temp_bytes(int32_t n) {
-  size_t bytes = 0;
-  hipcub::CountingInputIterator<int32_t> it(0);
-  (void)hipcub::DeviceSelect::Flagged(nullptr, bytes, it, (const uint8_t*)nullptr, (int32_t*)nullptr,
-                                (int32_t*)nullptr, n);
-  return bytes;
+  const size_t nt = ((size_t)(n > 0 ? n : 1) + kCmpTile - 1) / kCmpTile;
+  return 2 * sizeof(uint32_t) * nt + 256;
 }
 
 hipError_t compact(hipStream_t st, const uint8_t* flags, int32_t n, int32_t* out, int32_t* d_count,
                    void* temp, size_t temp_bytes) {
-  hipcub::CountingInputIterator<int32_t> it(0);
-  return hipcub::DeviceSelect::Flagged(temp, temp_bytes, it, flags, out, d_count, n, st);
+  const int32_t nt = (int32_t)(((size_t)(n > 0 ? n : 1) + kCmpTile - 1) / kCmpTile);
+  if (temp_bytes < compact_temp_bytes(n)) return hipErrorInvalidValue;
+  uint32_t* tile_count = static_cast<uint32_t*>(temp);
+  uint32_t* tile_off = tile_count + nt;
+  k_cmp_count<<<nt, kBlock, 0, st>>>(flags, n, tile_count);
+  k_cmp_scan<<<1, 1024, 0, st>>>(tile_count, nt, tile_off, d_count);
+  k_cmp_write<<<nt, kBlock, 0, st>>>(flags, n, tile_off, out);
+  return hipGetLastError();
 }
 
 }  // namespace vi
