@@ -405,12 +405,13 @@ vi_status vi_pca_basis(vi_ctx* ctx, int32_t level, int32_t d, int32_t n_max, int
  *   counts (dev) [n_ref] uint64, overwritten
  * pw * ph * pt in [1, 128]; mu in [0, 255]; W, H, T >= 1 with
  * W * H * T < 2^30; 0 <= n_ref < 2^24.  A volume smaller than the patch
- * has no candidates (every count 0); n_ref = 0 does nothing.  Enqueued on
- * hip_stream (NULL = the null stream): returns after enqueue, allocates
- * nothing and keeps no state; the caller keeps the buffers alive until the
- * stream reaches the call.
+ * has no candidates (every count 0); n_ref = 0 does nothing.  Runs on
+ * hip_stream (NULL = the null stream) and syncs it; the references are
+ * packed into n_ref x 132 bytes of device memory from the library's pool
+ * for the duration of the call.  The reference-candidate inner products
+ * run on the matrix cores (8-bit integer products, exact).
  * Errors: VI_E_INVAL (a null pointer with n_ref > 0, sizes out of range),
- * VI_E_HIP (launch failure). */
+ * VI_E_NOMEM, VI_E_HIP. */
 vi_status vi_closer_than_constant(const uint8_t* ref, int32_t n_ref, const uint8_t* vol,
                                   int32_t W, int32_t H, int32_t T, int32_t pw, int32_t ph,
                                   int32_t pt, int32_t mu, uint64_t* counts, void* hip_stream);

@@ -23,6 +23,10 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 
+# per-source flags: the App. B kernel keeps matrix-core results in ordinary
+# vector registers (no copies out of the accumulation registers)
+EXTRA = {"vi_appb.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
 
 def build(verbose: bool = False) -> str:
     objs = []
@@ -30,7 +34,8 @@ def build(verbose: bool = False) -> str:
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-x", "hip", "-c", os.path.join(CSRC, src),
+               "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

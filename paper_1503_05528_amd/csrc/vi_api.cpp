@@ -1049,9 +1049,19 @@ vi_status vi_closer_than_constant(const uint8_t* ref, int32_t n_ref, const uint8
   if (mu < 0 || mu > 255) return fail(VI_E_INVAL, "mu in [0, 255]");
   if (W < 1 || H < 1 || T < 1 || (int64_t)W * H * T >= (int64_t(1) << 30))
     return fail(VI_E_INVAL, "W, H, T >= 1 and W * H * T < 2^30");
-  const vi_status st = vi::closer_than_constant(
-      ref, n_ref, vol, W, H, T, pw, ph, pt, mu, reinterpret_cast<unsigned long long*>(counts),
-      static_cast<hipStream_t>(hip_stream));
+  if (n_ref == 0) return VI_OK;
+  // the packed references: a workspace from the library's pool, released
+  // once the stream has passed the call
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(VI_E_HIP, "no current device");
+  void* work = vi::pool_alloc(dev, vi::closer_work_bytes(n_ref));
+  if (!work) return fail(VI_E_NOMEM, "device allocation of the reference workspace failed");
+  hipStream_t hs = static_cast<hipStream_t>(hip_stream);
+  vi_status st = vi::closer_than_constant(ref, n_ref, vol, W, H, T, pw, ph, pt, mu,
+                                          reinterpret_cast<unsigned long long*>(counts), work,
+                                          hs);
+  if (hipStreamSynchronize(hs) != hipSuccess && st == VI_OK) st = VI_E_HIP;
+  vi::pool_free(dev, work);
   return st == VI_OK ? VI_OK : fail(st, "vi_closer_than_constant: launch failed");
 }
 

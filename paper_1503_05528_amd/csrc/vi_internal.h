@@ -236,10 +236,13 @@ vi_status align_unwarp(const uint8_t* aligned, const uint8_t* rgb, const uint8_t
                        hipStream_t st);
 
 // The textured-patch count of App. B (vi_appb.hip); arguments checked by
-// the caller.
+// the caller; work: closer_work_bytes(n_ref) bytes of device memory for the
+// packed references.
+size_t closer_work_bytes(int32_t n_ref);
 vi_status closer_than_constant(const uint8_t* ref, int32_t n_ref, const uint8_t* vol, int32_t W,
                                int32_t H, int32_t T, int32_t pw, int32_t ph, int32_t pt,
-                               int32_t mu, unsigned long long* counts, hipStream_t st);
+                               int32_t mu, unsigned long long* counts, void* work,
+                               hipStream_t st);
 
 // Dimensionality-reduced patch space (vi_reduce.hip).  A basis on the
 // device: Qp [rows][kPairs][dp] int32 (rows = dim / 25 patch rows (dt, dy);
