@@ -131,7 +131,7 @@ def summarize_counters(d):
     return out
 
 
-PASS_KERNEL = "vi::k_pass<false>"
+PASS_KERNEL = "vi::k_pass<false, false>"
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_BYTES = 1 << 30
 SQ_COUNTERS = "SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VMEM_RD SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT GRBM_GUI_ACTIVE"
@@ -195,7 +195,7 @@ def assemble_counters(pass_fetch, pass_write, pass_sq, copy_fetch, copy_write, w
             f"cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --kernel-include-regex k_pass "
             f"--output-format csv -d /tmp/p_FETCH_SIZE -o run -- python $REPO/bench.py "
             f"--config {workload} --no-sd --no-cpu-baseline --no-batched --no-served "
-            f"--steps 1 --warmup 0",
+            f"--no-realign --no-appb --no-image --no-reduced --steps 1 --warmup 0",
             "(the same with --pmc WRITE_SIZE, and with --pmc " + SQ_COUNTERS + ")",
             "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv "
             "-d /tmp/c_FETCH_SIZE -o run -- python $REPO/bench.py --copy-calibration "
@@ -803,7 +803,7 @@ def roofline_of(workload, pass_evals, pass_units, pass_ms, pass_launches, nomina
         "bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": unit,
         "frac": round(achieved / peak, 4),
         "traffic": None if cnt is None else cnt["hbm_bytes_per_launch"],
-        "kernel": "k_pass<false> (propagation pass with fused random search)",
+        "kernel": "k_pass<false, false> (propagation pass with fused random search, exact distance)",
         "avg_launch_ms": round(avg_ms, 5), "launches": pass_launches,
         "evals_per_launch": round(evals_per_launch, 1),
         "target_passes_per_launch": round(targets_per_launch, 1),
