@@ -50,6 +50,11 @@ def parse():
     ap.add_argument("--config", default="hd", choices=["sd", "hd", "tiny"])
     ap.add_argument("--no-realign", action="store_true",
                     help="skip the realignment measurement (Sec. 3.4)")
+    ap.add_argument("--reduce-dims", type=int, default=0,
+                    help="run the main workload in the PCA-reduced patch space (profiling; "
+                         "the headline is the exact method)")
+    ap.add_argument("--appb-only", action="store_true",
+                    help="only the textured-patch experiment (App. B), then exit")
     ap.add_argument("--no-reduced", action="store_true",
                     help="skip the PCA-reduced patch space measurement (Sec. 5)")
     ap.add_argument("--no-image", action="store_true",
@@ -950,11 +955,14 @@ def main():
         return
 
     vi.lib()
+    if a.appb_only:
+        print(json.dumps(measure_appb()), flush=True)
+        return
     if a.served_sweep:
         rates = [float(r) for r in a.served_sweep.split(",")]
         print(json.dumps(served_sweep(rates, a.served_jobs, a.em_iters)), flush=True)
         return
-    m = measure_plain(a.config, a.steps, a.warmup, a.em_iters)
+    m = measure_plain(a.config, a.steps, a.warmup, a.em_iters, reduce_dims=a.reduce_dims)
     clip, levels = m.pop("clip")
     line = {
         "metric": "NNF patch-distance evals/s (nominal)",
