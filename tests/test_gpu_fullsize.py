@@ -28,7 +28,11 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-4
 # the configurations bench.py times
 PARAMS = {"sd": dict(levels=4, em_tol=-1.0, em_max_iters=20, seed=1),
-          "hd": dict(levels=5, em_tol=-1.0, em_max_iters=20, seed=1)}
+          "hd": dict(levels=5, em_tol=-1.0, em_max_iters=20, seed=1),
+          "image 1920x1080": dict(levels=5, em_tol=-1.0, em_max_iters=20, seed=1,
+                                  patch=(5, 5, 1)),
+          "image 3840x2160": dict(levels=6, em_tol=-1.0, em_max_iters=20, seed=1,
+                                  patch=(5, 5, 1))}
 
 
 @pytest.fixture(scope="module")
@@ -118,6 +122,77 @@ def test_sd_full_level_bitexact(vi):
 @pytest.mark.timeout(900)
 def test_hd_full_level_bitexact(vi):
     check_full_level(vi, "hd", synth.hd())
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("W,H,levels", [(1920, 1080, 5), (3840, 2160, 6)])
+def test_image_full_level_bitexact(vi, W, H, levels):
+    # the still images bench.py times (5x5x1 patches, T = 1)
+    check_full_level(vi, f"image {W}x{H}", synth.image(31, W, H, frac=0.05, levels=levels))
+
+
+def _features_by_definition(rgbt, Q, voxels):
+    """Features of the given voxels from their clamped patch vectors."""
+    T, H, W, _ = rgbt.shape
+    out = []
+    for p in voxels:
+        t, r = divmod(int(p), H * W)
+        y, x = divmod(r, W)
+        xs = []
+        for dt in range(-2, 3):
+            for dy in range(-2, 3):
+                for dx in range(-2, 3):
+                    tt, yy, xx = (min(max(t + dt, 0), T - 1), min(max(y + dy, 0), H - 1),
+                                  min(max(x + dx, 0), W - 1))
+                    xs.append(rgbt[tt, yy, xx].astype(np.int64))
+        xv = np.concatenate(xs)
+        out.append((Q.astype(np.int64) @ xv + 128) // 256)
+    return np.array(out)
+
+
+@pytest.mark.timeout(900)
+def test_hd_reduced_search_sampled(vi):
+    """The HD clip's finest level in the reduced patch space with the
+    oracle's 16-dimensional PCA basis (8192 sampled sources): the GPU's
+    features of sampled voxels equal their definition, and after one
+    reduced search from the oracle's transition state every sampled target
+    holds a source match whose stored distance and count are the exact
+    patch distance of that match (vio_patch_ssd)."""
+    from oracle import pca
+    prm = PARAMS["hd"]
+    clip = synth.hd()
+    video, mask = clip.occluded_input(), clip.mask
+    print("[case] hd reduced: oracle set-up and basis", flush=True)
+    o = vio.Oracle(video, mask, **prm)
+    S1, S2, n = o.pca_moments(0, 8192)
+    _, B = pca.basis(pca.covariance(S1, S2, n, 50), 16)
+    Q = pca.quantize(B, 50)
+    o.set_state(1, rgbt=forced_level1(o, 5))
+    o.nnf_search(1, 0)
+    o.transition(0)
+    g = vi.Clip(dev(video), dev(mask), **prm)
+    g.set_state(0, *o.get_state(0))
+    g.set_reduction(0, Q)
+    rgbt = o.get_state(0)[0]
+    rng = np.random.default_rng(7)
+    V = rgbt.shape[0] * rgbt.shape[1] * rgbt.shape[2]
+    sample = np.concatenate([rng.integers(0, V, 300), [0, V - 1]])
+    f = g.features(0, 16).reshape(V, 16)[torch.from_numpy(sample).cuda()]
+    assert np.array_equal(host(f), _features_by_definition(rgbt, Q, sample))
+    del f
+    print("[case] hd reduced: GPU search of the finest level", flush=True)
+    g.nnf_search(0, em_iter=0)
+    _, gc, gd, gn = (host(t) for t in g.get_state(0))
+    hole, dsrc, htil = o.sets(0)
+    targets = np.flatnonzero(htil.ravel())
+    pick = targets[rng.integers(0, len(targets), 2000)]
+    for p in pick:
+        c = int(gc.ravel()[p])
+        assert dsrc.ravel()[c]
+        d, nv = o.patch_ssd(0, p, c)
+        assert d == int(gd.ravel()[p]) and nv == int(gn.ravel()[p]), p
+    g.close()
+    o.close()
 
 
 def test_sd_inpainting_keeps_known_pixels(vi):
