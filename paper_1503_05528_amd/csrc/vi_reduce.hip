@@ -16,8 +16,9 @@
 //   covariance  C_ij = (w_i w_j) (S2_ij / n - (S1_i / n)(S1_j / n)), double
 //               precision, each operation rounded on its own
 //   basis       orthogonal iteration on C (one workgroup, a thread per
-//               coordinate; products with C, then classical Gram-Schmidt
-//               applied twice), from a fixed pseudo-random start
+//               coordinate, the iterate in LDS; products with C, classical
+//               Gram-Schmidt applied twice after every fourth product and
+//               after the last), from a fixed pseudo-random start
 //   quantised   Q[k][i] = rint(256 w_i b_ik)
 //   features    f_k(p) = (sum_i Q[k][i] x_i(p) + 128) >> 8, exact int32
 //               (the caller's basis is checked so that no sum overflows),

@@ -559,8 +559,8 @@ def closer_than_constant(ref: torch.Tensor, vol: torch.Tensor, patch, mu: int = 
     patches V of the grey volume ``vol`` [T][H][W] (uint8, device) with
     SSD(ref[r], V) < SSD(ref[r], Z), Z the constant patch of value ``mu``.
     ``ref`` is [n][pt][ph][pw] (or [n][pw*ph*pt]) uint8 on the device and
-    ``patch`` = (pw, ph, pt).  Returns int64 counts (device); enqueued on
-    ``stream`` (default: the current stream) without a sync."""
+    ``patch`` = (pw, ph, pt).  Returns int64 counts (device); runs on
+    ``stream`` (default: the current stream) and synchronises it."""
     pw, ph, pt = (int(v) for v in patch)
     n = ref.shape[0]
     if ref.numel() != n * pw * ph * pt:
