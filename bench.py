@@ -900,6 +900,7 @@ def measure_plain(config, steps, warmup, em_iters, temporal=False, reduce_dims=0
     hole = torch.from_numpy(clip.mask).cuda().bool()
     err = (last["out"][hole].float() - torch.from_numpy(clip.video).cuda()[hole].float())
     hole_err = float(err.abs().mean())
+    hole_psnr = float(10.0 * torch.log10(255.0 ** 2 / (err * err).mean()))
     return {
         "value": nominal / elapsed, "ms_per_step": 1000.0 * elapsed / steps,
         "clips_per_s": steps / elapsed, "steps": steps, "warmup": warmup,
@@ -908,6 +909,7 @@ def measure_plain(config, steps, warmup, em_iters, temporal=False, reduce_dims=0
                     f"{f' compared in a {reduce_dims}-dimensional PCA space' if reduce_dims else ''}"
                     f", {em_iters} EM iterations per level, one clip per step",
         "hole_mean_abs_error": hole_err,
+        "hole_psnr_db": hole_psnr,
         "create_ms": 1000 * last["create_s"],
         "latency_p50_ms": 1000 * percentile(lat, 0.5),
         "latency_p99_ms": 1000 * percentile(lat, 0.99),
@@ -984,6 +986,7 @@ def main():
         "latency_samples": m["latency_samples"],
         "effective_evals_per_s": m["effective_evals_per_s"],
         "hole_mean_abs_error": m["hole_mean_abs_error"],
+        "hole_psnr_db": m["hole_psnr_db"],
         "kernel_ms_per_step": m["kernel_ms_per_step"],
         "kernel_ms_per_step_by_level": m["kernel_ms_per_step_by_level"],
         "roofline": m["roofline"],
@@ -1016,7 +1019,8 @@ def main():
         r = measure_plain(a.config, 2, 1, a.em_iters, reduce_dims=16)
         r.pop("clip")
         line["reduced"] = {k: r[k] for k in ("workload", "value", "ms_per_step", "create_ms",
-                                             "kernel_ms_per_step", "hole_mean_abs_error")}
+                                             "kernel_ms_per_step", "hole_mean_abs_error",
+                                             "hole_psnr_db")}
         line["reduced"]["exact_hole_mean_abs_error"] = m["hole_mean_abs_error"]
         line["reduced"]["exact_ms_per_step"] = m["ms_per_step"]
     if not a.no_image:
