@@ -537,6 +537,26 @@ def measure_image(steps=3, em_iters=20):
     return {"workload": "still images, 5x5x1 patches, 20 EM iterations per level", "rows": res}
 
 
+def image_cpu_baseline():
+    """CPU baseline leg of the image workload: the oracle's search of the
+    1920x1080 image's finest level (every target, matches drawn at random
+    first), on all host cores."""
+    from oracle import vio
+    from paper_1503_05528_amd import synth
+    img = synth.image(31, 1920, 1080, frac=0.05, levels=5)
+    o = vio.Oracle(img.occluded_input(), img.mask, levels=5, patch=(5, 5, 1), seed=1)
+    (_, _, _), (_, nS, _) = o.info(0)
+    c0 = time.perf_counter()
+    o.nnf_search(0, 0)
+    dt = time.perf_counter() - c0
+    # nominal evaluations of one search: |H~| (1 + sum_k (6 n_jf + [radius >= 1]))
+    r_max = 1920
+    per = 1 + sum(6 * 3 + (1 if int(r_max * 0.5 ** k) >= 1 else 0) for k in range(1, 11))
+    return {"value": nS * per / dt, "unit": "evals/s", "cores": vio.num_threads(),
+            "kind": "oracle",
+            "sample": f"vio_nnf_search of the 1920x1080 image's finest level ({nS} targets)"}
+
+
 def realign_cpu_baseline():
     """CPU baseline leg of the realignment: the oracle's estimation and warp
     of the same clip on all host cores."""
@@ -1051,6 +1071,8 @@ def main():
             line["realign"]["cpu_baseline"] = realign_cpu_baseline()
         if "appb" in line:
             line["appb"]["cpu_baseline"] = appb_cpu_baseline()
+        if "image" in line:
+            line["image"]["cpu_baseline"] = image_cpu_baseline()
     print(json.dumps(line), flush=True)
 
 
