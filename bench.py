@@ -17,7 +17,7 @@ propagation-pass kernel, timed with HIP events on the context's stream over
 the timed steps (one event pair around the back-to-back passes of each
 search; the average launch duration is their time over their count); its
 binding roof is the one the hardware counters of the same kernel show
-nearer to saturation (HBM traffic against the box's copy rate, or VALU
+nearer to saturation (HBM traffic against the device's measured copy rate, or VALU
 issue).  The CPU baseline is the oracle's search over a sample of the
 finest level's targets of the same clip, on all host cores and on one.
 """
