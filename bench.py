@@ -576,7 +576,7 @@ def realign_cpu_baseline():
 
 # App. B table: probability that a random patch beats the constant patch
 # (white noise of grey-level variance 25), as printed
-APPB_PAPER = [((3, 3, 1), 8e-2), ((5, 5, 1), 1e-2), ((3, 3, 3), 6e-3), ((7, 7, 1), 4.1e-4),
+APPB_PRINTED = [((3, 3, 1), 8e-2), ((5, 5, 1), 1e-2), ((3, 3, 3), 6e-3), ((7, 7, 1), 4.1e-4),
               ((9, 9, 1), 5.5e-6), ((11, 11, 1), 3e-7), ((5, 5, 5), 2e-7)]
 APPB_SIDE = 256
 APPB_REFS = 4096
@@ -597,7 +597,7 @@ def measure_appb(steps=3):
     vol = torch.from_numpy(synth.noise(170, (n, n, n))).cuda()
     rows = []
     total_pairs, total_s = 0, 0.0
-    for patch, printed in APPB_PAPER:
+    for patch, printed in APPB_PRINTED:
         pw, ph, pt = patch
         N = pw * ph * pt
         n_cand = (n - pw + 1) * (n - ph + 1) * (n - pt + 1)
