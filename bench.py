@@ -783,8 +783,7 @@ def percentile(xs, q):
     return ys[min(k, len(ys)) - 1]
 
 
-def roofline_of(workload, pass_evals, pass_units, pass_ms, pass_launches, nominal,
-                targets_per_search):
+def roofline_of(workload, pass_evals, pass_units, pass_ms, pass_launches, nominal_pass):
     """Roofline record of the propagation-pass kernel from a run's device
     counters and event times, and the counter record of the same kernel
     (profiles/k_pass_<workload>_counters.json) while its source matches."""
@@ -795,9 +794,9 @@ def roofline_of(workload, pass_evals, pass_units, pass_ms, pass_launches, nomina
                         + BYTES_PER_TARGET_PASS * targets_per_launch)
     gbs = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     tops = OPS_PER_EVAL * evals_per_launch / (avg_ms * 1e-3) / 1e12
-    # nominal evaluations of the passes: all of a step's minus one per target
-    # per search (step 0); the onion peel's share (< 1 %) is included
-    nominal_pass_per_launch = (nominal - targets_per_search) / pass_launches
+    # nominal evaluations of these launches (the onion peel's share, < 1 %,
+    # is included)
+    nominal_pass_per_launch = nominal_pass / pass_launches
     cnt = None
     path = counters_json(workload)
     if os.path.exists(path):
@@ -892,7 +891,8 @@ def measure_plain(config, steps, warmup, em_iters, temporal=False, reduce_dims=0
         recs += rec
         nominal += cnt["nominal_evals"]
         effective += cnt["effective_evals"]
-        pass_evals += cnt["pass_evals"]
+        # the one-lane form's distances (small levels take the wide form)
+        pass_evals += cnt["pass_evals"] - cnt["pass_wide_evals"]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -908,14 +908,33 @@ def measure_plain(config, steps, warmup, em_iters, temporal=False, reduce_dims=0
     kinds = by_kind(recs)
     # per kind and level: one more step, after the timed region, with every
     # kind timed
-    _, all_recs, _ = one_step(profile=tuple(vi.KERNEL_KINDS.values()))
+    _, all_recs, all_cnt = one_step(profile=tuple(vi.KERNEL_KINDS.values()))
     by_level = {}
     for kind, lvl, units, ms, nl in all_recs:
         key = f"{kind}@L{lvl}"
         by_level[key] = round(by_level.get(key, 0.0) + ms, 3)
     pas = kinds.get("pass", {"launches": 1, "units": 0, "ms": 1.0, "targets_per_search": 0})
-    roof = roofline_of(config, pass_evals, pas["units"], pas["ms"], pas["launches"], nominal,
-                       pas["targets_per_search"])
+    # the one-lane form's share of the passes' nominal evaluations: every
+    # target-pass of a search has the same nominal count, and every search
+    # one per target more (step 0), so the passes' nominal evaluations split
+    # by target-passes
+    ak = by_kind(all_recs)
+    one, wide = ak.get("pass", {}), ak.get("pass_wide", {})
+    u1, uw = one.get("units", 0), wide.get("units", 0)
+    tps = one.get("targets_per_search", 0) + wide.get("targets_per_search", 0)
+    nominal_one = (nominal - steps * tps) * (u1 / max(u1 + uw, 1))
+    roof = roofline_of(config, pass_evals, pas["units"], pas["ms"], pas["launches"], nominal_one)
+    pass_wide = None
+    if wide:
+        pass_wide = {
+            "kernel": "k_pass_wide<64> (the same pass on small target lists, eight lanes per "
+                      "distance)",
+            "launches_per_step": wide["launches"], "ms_per_step": round(wide["ms"], 3),
+            "avg_launch_ms": round(wide["ms"] / wide["launches"], 5),
+            "target_passes_per_launch": round(uw / wide["launches"], 1),
+            "evals_per_launch": round(all_cnt["pass_wide_evals"] / wide["launches"], 1),
+            "levels": sorted({lvl for kind, lvl, _, _, _ in all_recs if kind == "pass_wide"}),
+        }
     # mean |error| over the hole's colour channels against the clip's true video
     hole = torch.from_numpy(clip.mask).cuda().bool()
     err = (last["out"][hole].float() - torch.from_numpy(clip.video).cuda()[hole].float())
@@ -938,6 +957,7 @@ def measure_plain(config, steps, warmup, em_iters, temporal=False, reduce_dims=0
         "kernel_ms_per_step": {k: round(v["ms"], 3) for k, v in by_kind(all_recs).items()},
         "kernel_ms_per_step_by_level": by_level,
         "roofline": roof,
+        "pass_wide": pass_wide,
         "clip": (clip, levels),
     }
 
@@ -1010,6 +1030,7 @@ def main():
         "kernel_ms_per_step": m["kernel_ms_per_step"],
         "kernel_ms_per_step_by_level": m["kernel_ms_per_step_by_level"],
         "roofline": m["roofline"],
+        "pass_wide": m["pass_wide"],
         "cpu_baseline": None,
     }
     sd_clip = None
@@ -1022,6 +1043,7 @@ def main():
         line["sd"]["roofline"] = {k: s["roofline"][k] for k in
                                   ("bound", "achieved", "peak", "unit", "frac", "traffic",
                                    "avg_launch_ms", "algorithmic_frac_of_hbm_peak", "counters")}
+        line["sd"]["pass_wide"] = s["pass_wide"]
         line["sd"]["ms_per_step_service"] = s["latency_p50_ms"]
     elif a.config == "sd":
         sd_clip = (clip, levels)

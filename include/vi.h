@@ -85,6 +85,12 @@ typedef struct {
                            sources, 32 steps of orthogonal iteration; see
                            vi_pca_basis), and the searches of the EM loop
                            compare those features (vi_set_reduction) */
+  int32_t wide_pass_max; /* execution only, results do not depend on it:
+                            -1 (default) lets the library choose; otherwise
+                            the unmasked exact passes over at most this many
+                            targets compute each candidate's distance with
+                            eight lanes (every row load at once) instead of
+                            one lane with early exit (0: never) */
 } vi_params;
 
 typedef struct vi_ctx vi_ctx; /* one clip: all its device state */
@@ -427,6 +433,8 @@ typedef struct {
   int64_t pass_evals;      /* of effective_evals: propagation and random-search passes */
   int64_t init_evals;      /* of effective_evals: step 0 of the EM-loop searches */
   int64_t onion_evals;     /* of effective_evals: onion-peel searches */
+  int64_t pass_wide_evals; /* of pass_evals: passes of the wide form (see
+                              vi_params.wide_pass_max) */
 } vi_counters;
 vi_status vi_get_counters(vi_ctx* ctx, vi_counters* out);
 vi_status vi_reset_counters(vi_ctx* ctx);
@@ -440,7 +448,9 @@ typedef enum {
   VI_K_PASS = 1,   /* propagation / random-search pass; units = targets x passes */
   VI_K_RECON = 2,  /* reconstruction; units = hole pixels */
   VI_K_OTHER = 3,  /* upsampling, copies; units = voxels */
-  VI_K_ONION = 4   /* any launch of the onion-peel initialisation */
+  VI_K_ONION = 4,  /* any launch of the onion-peel initialisation */
+  VI_K_PASS_WIDE = 5 /* VI_K_PASS in the wide form (small target lists, see
+                        vi_params.wide_pass_max) */
 } vi_kernel_kind;
 typedef struct {
   int32_t kind;  /* vi_kernel_kind */
@@ -450,7 +460,7 @@ typedef struct {
   int32_t launches; /* launches the record covers */
 } vi_kernel_time;
 /* kinds: bit mask of the vi_kernel_kind values timed (1 << kind), 0 = off */
-#define VI_PROFILE_ALL 0x1F
+#define VI_PROFILE_ALL 0x3F
 vi_status vi_profile(vi_ctx* ctx, int32_t kinds);
 /* Copies up to cap records (host) of the launches timed since the last read
  * and clears them; returns the number of records or a negative status.

@@ -76,14 +76,15 @@ struct vi_ctx {
   size_t ctemp_bytes = 0;
   int32_t* d_count = nullptr;             // [2]
   unsigned long long* d_u64 = nullptr;    // [0] |change| sum, [1..2] set_state checks,
-                                          // [3..5] evaluation sums: passes, step 0, onion
+                                          // [3..6] evaluation sums: one-lane passes, step
+                                          // 0, onion, wide passes
   unsigned long long* d_cnt = nullptr;    // spread counters (kCntWords words each):
-                                          // [0] |change|, [1..3] evaluations as d_u64[3..5]
+                                          // [0] |change|, [1..4] evaluations as d_u64[3..6]
   // onion-peel scratch (coarsest level)
   uint8_t *o_Hp = nullptr, *o_E = nullptr, *o_bd = nullptr, *o_S = nullptr;
   uint8_t *o_t1 = nullptr, *o_t2 = nullptr;
   int32_t *o_tl = nullptr, *o_pl = nullptr;
-  // work counters (host side; effective evaluations live in d_cnt[1..3])
+  // work counters (host side; effective evaluations live in d_cnt[1..4])
   int64_t n_nominal = 0, n_searches = 0, n_em = 0, n_recon = 0;
   // kernel timing with events on the context's stream
   uint32_t prof_mask = 0;  // kernel kinds timed (bit 1 << vi_kernel_kind)
@@ -196,6 +197,7 @@ vi_status check_params(const vi_params* p) {
     return fail(VI_E_INVAL, "temporal_subsample must be 0 or 1");
   if (p->reduce_dims < 0 || p->reduce_dims > vi::kMaxRed)
     return fail(VI_E_INVAL, "reduce_dims must be in [0, 32]");
+  if (p->wide_pass_max < -1) return fail(VI_E_INVAL, "wide_pass_max must be >= -1");
   return VI_OK;
 }
 
@@ -276,15 +278,17 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
   A.smask = smask;
   A.excl = excl;
   A.step = step;
-  // onion searches (masked) count apart from the EM loop's
-  unsigned long long* ev_pass = c->d_cnt + (size_t)(excl ? 3 : 1) * vi::kCntWords;
+  // the reduced distance (unmasked searches of a level with a basis): the
+  // targets' features on the current video first
+  const bool red = d.rd > 0 && !excl;
+  // onion searches (masked) count apart from the EM loop's, and the EM
+  // loop's passes of the wide form apart from the one-lane form's
+  const bool wide = vi::pass_is_wide(nS, excl != nullptr, red, c->prm.wide_pass_max);
+  unsigned long long* ev_pass = c->d_cnt + (size_t)(excl ? 3 : (wide ? 4 : 1)) * vi::kCntWords;
   unsigned long long* ev_init = c->d_cnt + (size_t)(excl ? 3 : 2) * vi::kCntWords;
   A.evals = ev_init;
   A.nin = d.nnf0;
   A.nout = d.nnf0;
-  // the reduced distance (unmasked searches of a level with a basis): the
-  // targets' features on the current video first
-  const bool red = d.rd > 0 && !excl;
   int r;
   if (red) {
     r = prof_begin(c, VI_K_OTHER);
@@ -300,7 +304,8 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
   int2* buf[2] = {d.nnf0, d.nnf1};
   int cur = 0;
   // the passes run back to back: one event pair covers all of them
-  r = prof_begin(c, VI_K_PASS);
+  const int32_t pass_kind = wide ? VI_K_PASS_WIDE : VI_K_PASS;
+  r = prof_begin(c, pass_kind);
   int64_t pass_units = 0;
   int32_t n_pass = 0;
   int32_t t = 0;
@@ -320,7 +325,7 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
       // previous pass at the same stride
       A.t = ++t;
       A.since = (c->prm.n_jf > 0 && t > np) ? t - np : 0;
-      vi::launch_pass(c->st, d, A, red);
+      vi::launch_pass(c->st, d, A, red, c->prm.wide_pass_max);
       pass_units += (int64_t)nS;
       ++n_pass;
       VI_TRY(launched("pass"));
@@ -328,7 +333,7 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
     }
   }
   if (n_pass > 0)
-    prof_end(c, r, VI_K_PASS, level, pass_units, n_pass);
+    prof_end(c, r, pass_kind, level, pass_units, n_pass);
   else if (r >= 0)
     c->recs.pop_back();
   if (cur == 1) {
@@ -676,6 +681,7 @@ vi_status vi_params_default(vi_params* o) {
   o->seed = 0;
   o->temporal_subsample = 0;
   o->reduce_dims = 0;
+  o->wide_pass_max = -1;
   return VI_OK;
 }
 
@@ -771,10 +777,10 @@ vi_status vi_create(vi_ctx** out, const vi_params* prm, int32_t W, int32_t H, in
   const vi::DevLevel& L0 = c->lv[0].d;
   const size_t V0 = (size_t)L0.V;
   if ((st = dalloc(c, &c->d_count, 4)) || (st = dalloc(c, &c->d_u64, 8)) ||
-      (st = dalloc(c, &c->d_cnt, 4 * (size_t)vi::kCntWords)))
+      (st = dalloc(c, &c->d_cnt, 5 * (size_t)vi::kCntWords)))
     return bail(st);
   vi::launch_fill_u64(c->st, c->d_u64, 8);
-  vi::launch_fill_u64(c->st, c->d_cnt, 4 * vi::kCntWords);
+  vi::launch_fill_u64(c->st, c->d_cnt, 5 * vi::kCntWords);
   c->ctemp_bytes = vi::compact_temp_bytes(L0.V);
   if ((st = dalloc(c, reinterpret_cast<uint8_t**>(&c->ctemp), c->ctemp_bytes))) return bail(st);
   // creation temporaries
@@ -1223,26 +1229,27 @@ int64_t vi_nominal_evals(const vi_ctx* c, int32_t level) {
 
 vi_status vi_get_counters(vi_ctx* c, vi_counters* out) {
   if (!c || !out) return fail(VI_E_INVAL, "null argument");
-  unsigned long long v[3] = {0, 0, 0};
-  vi::launch_sum_spread(c->st, c->d_cnt + vi::kCntWords, 3, c->d_u64 + 3);
+  unsigned long long v[4] = {0, 0, 0, 0};
+  vi::launch_sum_spread(c->st, c->d_cnt + vi::kCntWords, 4, c->d_u64 + 3);
   VI_TRY(launched("counters"));
   VI_HIP(hipMemcpyAsync(v, c->d_u64 + 3, sizeof(v), hipMemcpyDeviceToHost, c->st));
   VI_TRY(sync(c));
   out->nominal_evals = c->n_nominal;
-  out->effective_evals = (int64_t)(v[0] + v[1] + v[2]);
+  out->effective_evals = (int64_t)(v[0] + v[1] + v[2] + v[3]);
   out->searches = c->n_searches;
   out->em_iters = c->n_em;
   out->recon_pixels = c->n_recon;
-  out->pass_evals = (int64_t)v[0];
+  out->pass_evals = (int64_t)(v[0] + v[3]);
   out->init_evals = (int64_t)v[1];
   out->onion_evals = (int64_t)v[2];
+  out->pass_wide_evals = (int64_t)v[3];
   return VI_OK;
 }
 
 vi_status vi_reset_counters(vi_ctx* c) {
   if (!c) return fail(VI_E_INVAL, "null context");
   c->n_nominal = c->n_searches = c->n_em = c->n_recon = 0;
-  vi::launch_fill_u64(c->st, c->d_cnt + vi::kCntWords, 3 * vi::kCntWords);
+  vi::launch_fill_u64(c->st, c->d_cnt + vi::kCntWords, 4 * vi::kCntWords);
   return launched("fill");
 }
 

@@ -418,6 +418,143 @@ struct PassShared {
   int32_t nq;
 };
 
+// Propagation candidates of one target (phase 1): candidate j (0..5) goes to
+// s_cand[slot * 6 + j], and the candidates that can win are appended to the
+// LDS queue as (slot | j << 8), grouped per wave and direction.  Reports
+// whether the target is stable and its own change mark.  Every lane of the
+// calling waves must call it together (wave ballots).
+template <bool MASKED>
+__device__ __forceinline__ void gather_candidates(const DevLevel& L, const PassArgs& A,
+                                                  bool active, int32_t p, int32_t px, int32_t py,
+                                                  int32_t pt, int2 inc, int slot,
+                                                  int32_t* s_cand, uint16_t* s_q, int32_t& s_nq,
+                                                  bool& stable, uint16_t& cp) {
+  const int32_t s = A.s;
+  int32_t c[6];
+  bool v[6];
+  int32_t qi[6];
+  bool qok[6];
+  // the gathers are unconditional (clamped to p), so the six neighbours'
+  // marks, then their entries, then the six source flags, are fetched
+  // together
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int axis = j >> 1;
+    const int32_t sgn = (j & 1) ? 1 : -1;
+    const int32_t coord = axis == 0 ? px : (axis == 1 ? py : pt);
+    const int32_t dim = axis == 0 ? L.W : (axis == 1 ? L.H : L.T);
+    const int32_t stride = axis == 0 ? 1 : (axis == 1 ? L.W : L.WH);
+    const int32_t qc = coord + sgn * s;
+    // nothing beats a perfect incumbent: (0, index 0) is the minimum
+    qok[j] = active && inc.y != 0 && qc >= 0 && qc < dim;
+    qi[j] = qok[j] ? p + sgn * s * stride : p;
+  }
+  uint16_t cg[6];
+  if (A.since > 0) {
+    cp = active ? L.chg[p] : (uint16_t)0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) cg[j] = L.chg[qi[j]];
+  }
+  if (MASKED) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) qok[j] = qok[j] && A.smask[qi[j]] != 0;
+  }
+  // Within a search the video is fixed, so distances are.  A target whose
+  // match is unchanged since its previous pass at this stride, and whose
+  // neighbours in the target set are unchanged since before that pass,
+  // sees exactly the candidates that lost to its match then: it keeps it.
+  // A neighbour's mark read while it is being rewritten only holds this
+  // pass (no skip).  Neighbours outside the target set give no candidate.
+  stable = A.since > 0 && active && cp <= A.since;
+  if (A.since > 0) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) stable = stable && (!qok[j] || cg[j] < A.since);
+  }
+  // a stable target needs neither its neighbours' matches nor the source
+  // flags of their candidates
+  int32_t cq[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    qok[j] = qok[j] && !stable;
+    cq[j] = -1;
+  }
+  if (!stable) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) cq[j] = A.nin[qi[j]].x;
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int axis = j >> 1;
+    const int32_t sgn = (j & 1) ? 1 : -1;
+    const int32_t stride = axis == 0 ? 1 : (axis == 1 ? L.W : L.WH);
+    // unmasked search: the target set is H~, where every entry holds a
+    // match after step 0 and every other entry holds -1 in both buffers
+    if (!MASKED) qok[j] = qok[j] && cq[j] >= 0;
+    c[j] = cq[j] - sgn * s * stride;
+    qok[j] = qok[j] && c[j] >= 0 && c[j] < L.V;
+  }
+  uint8_t ds[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) ds[j] = 0;
+  if (!stable) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) ds[j] = L.dsrc[qok[j] ? c[j] : 0];
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    bool ok = qok[j] && ds[j] && c[j] != inc.x;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (k < j) ok = ok && !(v[k] && c[k] == c[j]);
+    v[j] = ok;
+    s_cand[slot * 6 + j] = c[j];
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const uint64_t bal = __ballot(v[j]);
+    const int cnt = __popcll(bal);
+    int base = 0;
+    if ((threadIdx.x & 63) == 0 && cnt) base = atomicAdd(&s_nq, cnt);
+    base = __builtin_amdgcn_readlane(base, 0);
+    if (v[j]) s_q[base + lane_prefix(bal)] = (uint16_t)(slot | (j << 8));
+  }
+}
+
+// The random-search candidate of iteration A.rs_k around best_c (Eq. (3.1)):
+// a uniform draw per axis over the window of radius A.R clipped to the
+// centres whose patch lies inside the volume (Philox purpose 0).
+__device__ __forceinline__ int32_t random_candidate(const DevLevel& L, const PassArgs& A,
+                                                    int32_t p, int32_t best_c) {
+  int32_t cx, cy, ct;
+  unlin(L, best_c, cx, cy, ct);
+  const int32_t R = A.R;
+  const int32_t lox = max(2, cx - R), hix = min(L.W - 3, cx + R);
+  const int32_t loy = max(2, cy - R), hiy = min(L.H - 3, cy + R);
+  const int32_t lot = max(L.ht, ct - R), hit = min(L.T - 1 - L.ht, ct + R);
+  uint64_t w[4];
+  philox4x64_10((uint64_t)p, A.step, (uint64_t)A.rs_k, ((uint64_t)L.level << 8) | 0u, L.seed, 0,
+                w);
+  const int32_t rx = lox + draw_below(w[0], (uint32_t)(hix - lox + 1));
+  const int32_t ry = loy + draw_below(w[1], (uint32_t)(hiy - loy + 1));
+  const int32_t rt = lot + draw_below(w[2], (uint32_t)(hit - lot + 1));
+  return (rt * L.H + ry) * L.W + rx;
+}
+
+// The pass's result for one target: its entry in the output state and, when
+// its match changed, its marks.
+__device__ __forceinline__ void store_match(const DevLevel& L, const PassArgs& A, int32_t p,
+                                            bool stable, uint16_t cp, int2 inc, int32_t best_c,
+                                            uint32_t best_d) {
+  // A stable target unchanged for two passes already holds this entry in
+  // both buffers: the write is skipped.
+  if (!(stable && (int32_t)cp + 2 <= A.t && best_c == inc.x))
+    A.nout[p] = make_int2(best_c, (int32_t)best_d);
+  if (best_c != inc.x) {
+    L.chg[p] = (uint16_t)A.t;
+    L.rmark[p] = (uint8_t)L.repoch;
+  }
+}
+
 // One block of BLK consecutive targets (block index blk of the target list);
 // returns the evaluations this thread accounts for.  All threads of the
 // workgroup must call it together.
@@ -452,95 +589,8 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
   bool stable = false;
   uint16_t cp = 0;
   if (A.s > 0) {
-    const int32_t s = A.s;
-    int32_t c[6];
-    bool v[6];
-    int32_t qi[6];
-    bool qok[6];
-    // the gathers are unconditional (clamped to p), so the six neighbours'
-    // marks, then their entries, then the six source flags, are fetched
-    // together
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      const int axis = j >> 1;
-      const int32_t sgn = (j & 1) ? 1 : -1;
-      const int32_t coord = axis == 0 ? px : (axis == 1 ? py : pt);
-      const int32_t dim = axis == 0 ? L.W : (axis == 1 ? L.H : L.T);
-      const int32_t stride = axis == 0 ? 1 : (axis == 1 ? L.W : L.WH);
-      const int32_t qc = coord + sgn * s;
-      // nothing beats a perfect incumbent: (0, index 0) is the minimum
-      qok[j] = active && inc.y != 0 && qc >= 0 && qc < dim;
-      qi[j] = qok[j] ? p + sgn * s * stride : p;
-    }
-    uint16_t cg[6];
-    if (A.since > 0) {
-      cp = active ? L.chg[p] : (uint16_t)0;
-#pragma unroll
-      for (int j = 0; j < 6; ++j) cg[j] = L.chg[qi[j]];
-    }
-    if (MASKED) {
-#pragma unroll
-      for (int j = 0; j < 6; ++j) qok[j] = qok[j] && A.smask[qi[j]] != 0;
-    }
-    // Within a search the video is fixed, so distances are.  A target whose
-    // match is unchanged since its previous pass at this stride, and whose
-    // neighbours in the target set are unchanged since before that pass,
-    // sees exactly the candidates that lost to its match then: it keeps it.
-    // A neighbour's mark read while it is being rewritten only holds this
-    // pass (no skip).  Neighbours outside the target set give no candidate.
-    stable = A.since > 0 && active && cp <= A.since;
-    if (A.since > 0) {
-#pragma unroll
-      for (int j = 0; j < 6; ++j) stable = stable && (!qok[j] || cg[j] < A.since);
-    }
-    // a stable target needs neither its neighbours' matches nor the source
-    // flags of their candidates
-    int32_t cq[6];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      qok[j] = qok[j] && !stable;
-      cq[j] = -1;
-    }
-    if (!stable) {
-#pragma unroll
-      for (int j = 0; j < 6; ++j) cq[j] = A.nin[qi[j]].x;
-    }
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      const int axis = j >> 1;
-      const int32_t sgn = (j & 1) ? 1 : -1;
-      const int32_t stride = axis == 0 ? 1 : (axis == 1 ? L.W : L.WH);
-      // unmasked search: the target set is H~, where every entry holds a
-      // match after step 0 and every other entry holds -1 in both buffers
-      if (!MASKED) qok[j] = qok[j] && cq[j] >= 0;
-      c[j] = cq[j] - sgn * s * stride;
-      qok[j] = qok[j] && c[j] >= 0 && c[j] < L.V;
-    }
-    uint8_t ds[6];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) ds[j] = 0;
-    if (!stable) {
-#pragma unroll
-      for (int j = 0; j < 6; ++j) ds[j] = L.dsrc[qok[j] ? c[j] : 0];
-    }
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      bool ok = qok[j] && ds[j] && c[j] != inc.x;
-#pragma unroll
-      for (int k = 0; k < 6; ++k)
-        if (k < j) ok = ok && !(v[k] && c[k] == c[j]);
-      v[j] = ok;
-      s_cand[tid * 6 + j] = c[j];
-    }
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      const uint64_t bal = __ballot(v[j]);
-      const int cnt = __popcll(bal);
-      int base = 0;
-      if ((tid & 63) == 0 && cnt) base = atomicAdd(&s_nq, cnt);
-      base = __builtin_amdgcn_readlane(base, 0);
-      if (v[j]) s_q[base + lane_prefix(bal)] = (uint16_t)(tid | (j << 8));
-    }
+    gather_candidates<MASKED>(L, A, active, p, px, py, pt, inc, tid, s_cand, s_q, s_nq, stable,
+                              cp);
     __syncthreads();
     const int32_t nq = s_nq;
     for (int32_t e = tid; e < nq; e += BLK) {
@@ -568,19 +618,7 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
     // best_c >= 0 for every target once step 0 has run; a target without a
     // match (cand -1) is left to step 0 rather than searched around
     if (A.rs_k > 0 && best_c >= 0) {
-      int32_t cx, cy, ct;
-      unlin(L, best_c, cx, cy, ct);
-      const int32_t R = A.R;
-      const int32_t lox = max(2, cx - R), hix = min(L.W - 3, cx + R);
-      const int32_t loy = max(2, cy - R), hiy = min(L.H - 3, cy + R);
-      const int32_t lot = max(L.ht, ct - R), hit = min(L.T - 1 - L.ht, ct + R);
-      uint64_t w[4];
-      philox4x64_10((uint64_t)p, A.step, (uint64_t)A.rs_k, ((uint64_t)L.level << 8) | 0u, L.seed,
-                    0, w);
-      const int32_t rx = lox + draw_below(w[0], (uint32_t)(hix - lox + 1));
-      const int32_t ry = loy + draw_below(w[1], (uint32_t)(hiy - loy + 1));
-      const int32_t rt = lot + draw_below(w[2], (uint32_t)(hit - lot + 1));
-      const int32_t rc = (rt * L.H + ry) * L.W + rx;
+      const int32_t rc = random_candidate(L, A, p, best_c);
       // strictly better only: nothing beats distance 0.  The window keeps the
       // whole candidate patch inside the volume, so the distance can be
       // computed before the source test, which is only needed (and its
@@ -598,15 +636,214 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
       }
       ne += nr;
     }
-    // A stable target unchanged for two passes already holds this entry in
-    // both buffers: the write is skipped.
-    if (!(stable && (int32_t)cp + 2 <= A.t && best_c == inc.x))
-      A.nout[p] = make_int2(best_c, (int32_t)best_d);
-    if (best_c != inc.x) {
-      L.chg[p] = (uint16_t)A.t;
-      L.rmark[p] = (uint8_t)L.repoch;
+    store_match(L, A, p, stable, cp, inc, best_c, best_d);
+  }
+  return ne;
+}
+
+// ------------------------------------------------------------------------
+// The same pass for levels with few targets, where one workgroup per 256
+// targets leaves most compute units idle and a pass takes as long as the
+// longest chain of dependent fetches in a wave: a queued candidate with early
+// exit is up to 13 round trips, its random-search candidate 13 more.  Here a
+// group of kGrp lanes computes one candidate's full distance with every row
+// load in flight at once (one round trip), for the queued candidates and
+// then for the random-search candidates, and a workgroup of 256 lanes serves
+// TB targets.  Without early exit a losing candidate's distance is its full
+// distance instead of a partial sum above the bound: the same candidates win
+// with the same distances, and the same evaluations are counted.
+// ------------------------------------------------------------------------
+constexpr int kGrp = 8;
+
+// Rows of a video patch for the lanes of a group: slot k of lane g holds the
+// row with index 8k + g in the centre-out order of the one-lane distance,
+// coded (dt + 2) | (dy + 2) << 3 in six bits per lane; 63 marks no row.
+constexpr int8_t kCoDt[25] = {0, 0, 0, -1, 1, 0, 0, -1, -1, 1, 1, -2, 2,
+                              -1, -1, 1, 1, -2, -2, 2, 2, -2, -2, 2, 2};
+constexpr int8_t kCoDy[25] = {0, -1, 1, 0, 0, -2, 2, -1, 1, -1, 1, 0, 0,
+                              -2, 2, -2, 2, -1, 1, -1, 1, -2, 2, -2, 2};
+constexpr uint64_t slot_rows(int k) {
+  uint64_t v = 0;
+  for (int g = 0; g < 8; ++g) {
+    const int r = 8 * k + g;
+    const uint64_t code = r < 25 ? (uint64_t)((kCoDt[r] + 2) | ((kCoDy[r] + 2) << 3)) : 63u;
+    v |= code << (6 * g);
+  }
+  return v;
+}
+constexpr uint64_t kSlotRows[4] = {slot_rows(0), slot_rows(1), slot_rows(2), slot_rows(3)};
+
+// Patch distance (unmasked: target voxels outside the volume are not
+// compared) computed by the kGrp lanes of a group.  A video patch: first the
+// eight rows nearest the centre, one per lane; when the group's partial sum
+// already exceeds abort_above the evaluation stops there (the full distance
+// could only be larger, as in the one-lane form), otherwise the 17 other rows
+// follow, up to three per lane, all loads in flight at once.  An image patch:
+// its five rows on lanes 0-4.  The lanes' sums are added with DPP within
+// each group of eight lanes (quad swaps, then the half-row mirror), modulo
+// 2^32 like the one-lane sum, so the full distance is the same.  Returns the
+// full distance when it is <= abort_above, otherwise some value above it.
+// Every lane of the group must call it together with the same arguments.
+__device__ __forceinline__ uint32_t group_sum8(uint32_t d) {
+  d += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)d, 0xB1, 0xF, 0xF, false);   // [1,0,3,2]
+  d += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)d, 0x4E, 0xF, 0xF, false);   // [2,3,0,1]
+  d += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)d, 0x141, 0xF, 0xF, false);  // half mirror
+  return d;
+}
+
+template <int K0, int K1>
+__device__ __forceinline__ uint32_t group_rows(const DevLevel& L, int32_t p, int32_t py,
+                                               int32_t pt, int32_t c, int lg, uint32_t xm,
+                                               bool vid) {
+  const uint2* __restrict__ vox = L.vox;
+  Row5 a[K1 - K0], b[K1 - K0];
+  uint32_t okm[K1 - K0];
+#pragma unroll
+  for (int k = K0; k < K1; ++k) {
+    int dt, dy;
+    bool rv;
+    if (vid) {
+      const uint32_t code = (uint32_t)(kSlotRows[k] >> (6 * lg)) & 63u;
+      rv = code != 63u;
+      dt = rv ? (int)(code & 7u) - 2 : 0;
+      dy = rv ? (int)(code >> 3) - 2 : 0;
+    } else {
+      rv = lg < 5;
+      dt = 0;
+      dy = rv ? lg - 2 : 0;
+    }
+    const int32_t tt = pt + dt, yy = py + dy;
+    const bool rok = rv && tt >= 0 && tt < L.T && yy >= 0 && yy < L.H;
+    const int32_t row = dt * L.WH + dy * L.W;
+    okm[k - K0] = rok ? xm : 0u;
+    // no row: the centre rows (in the volume), masked; the video holds two
+    // voxels of padding on both sides
+    b[k - K0] = load_row5(vox + (c + row - 2));
+    a[k - K0] = load_row5(vox + ((rok ? p + row : p) - 2));
+  }
+  SsdAcc q{0u, 0u, 0};
+#pragma unroll
+  for (int k = 0; k < K1 - K0; ++k) {
+#pragma unroll
+    for (int x = 0; x < 5; ++x) {
+      const bool ok = (okm[k] >> x) & 1u;
+      acc_voxel(q, ok ? a[k].v[x] : make_uint2(0, 0), ok ? b[k].v[x] : make_uint2(0, 0));
     }
   }
+  return group_sum8(q.sc + (uint32_t)L.lambda * q.st);
+}
+
+__device__ __forceinline__ uint32_t group_ssd(const DevLevel& L, int32_t p, int32_t px, int32_t py,
+                                              int32_t pt, int32_t c, int lg,
+                                              uint32_t abort_above) {
+  const bool vid = L.ht != 0;
+  const int klo = px < 2 ? 2 - px : 0;
+  const int khi = px + 2 >= L.W ? L.W + 1 - px : 4;
+  const uint32_t xm = (0x1fu << klo) & (0x1fu >> (4 - khi));
+  const uint32_t d0 = group_rows<0, 1>(L, p, py, pt, c, lg, xm, vid);
+  if (!vid || d0 > abort_above) return d0;
+  return d0 + group_rows<1, 4>(L, p, py, pt, c, lg, xm, true);
+}
+
+template <int TB>
+struct WideShared {
+  PassShared<TB> s;
+  int32_t rc[TB];   // random-search candidate of the target, or -1
+  uint32_t rd[TB];  // its distance
+};
+
+// One block of TB consecutive targets with NT = kBlock lanes (unmasked exact
+// distance); returns the evaluations this thread accounts for.
+template <int TB>
+__device__ __forceinline__ int pass_block_wide(const DevLevel& L, const PassArgs& A, int32_t blk,
+                                               WideShared<TB>& wsh) {
+  static_assert(TB % 64 == 0 && TB <= kBlock, "targets per workgroup: whole waves");
+  PassShared<TB>& sh = wsh.s;
+  const int tid = threadIdx.x;
+  const bool tgt = tid < TB;  // wave-uniform
+  const int32_t i = blk * TB + tid;
+  const bool active = tgt && i < A.nS;
+  int32_t p = 0, px = 0, py = 0, pt = 0;
+  int2 inc = make_int2(0, 0);
+  if (tid == 0) sh.nq = 0;
+  if (active) {
+    p = A.tlist[i];
+    unlin(L, p, px, py, pt);
+    inc = A.nin[p];
+    sh.best[tid] = (unsigned long long)(uint32_t)inc.y << 3;
+  }
+  if (tgt) {
+    sh.p[tid] = p;
+    sh.xy[tid] = px | (py << 16);
+    sh.t[tid] = pt;
+  }
+  __syncthreads();
+  const int g = tid / kGrp, lg = tid % kGrp;
+  constexpr int kGroups = kBlock / kGrp;
+  int ne = 0;
+  bool stable = false;
+  uint16_t cp = 0;
+  if (A.s > 0) {
+    if (tgt)
+      gather_candidates<false>(L, A, active, p, px, py, pt, inc, tid, sh.cand, sh.q, sh.nq,
+                               stable, cp);
+    __syncthreads();
+    const int32_t nq = sh.nq;
+    for (int32_t e = g; e < nq; e += kGroups) {
+      const uint32_t ent = sh.q[e];
+      const int lt = ent & 255, j = ent >> 8;
+      const int32_t xy = sh.xy[lt];
+      // a candidate whose partial distance exceeds the current best cannot win
+      const uint32_t bound = (uint32_t)(sh.best[lt] >> 3);
+      const uint32_t d = group_ssd(L, sh.p[lt], xy & 0xFFFF, xy >> 16, sh.t[lt],
+                                   sh.cand[lt * 6 + j], lg, bound);
+      if (lg == 0 && d <= bound)
+        atomicMin(&sh.best[lt], ((unsigned long long)d << 3) | (unsigned long long)(j + 1));
+    }
+    if (tid == 0) ne += nq;
+    __syncthreads();
+  }
+  uint32_t best_d = 0;
+  int32_t best_c = -1;
+  int32_t rc = -1;
+  if (active) {
+    const unsigned long long key = sh.best[tid];
+    const int slot = (int)(key & 7);
+    best_d = (uint32_t)(key >> 3);
+    best_c = slot ? sh.cand[tid * 6 + slot - 1] : inc.x;
+    // as in the one-lane pass: no search around a missing match, and
+    // nothing beats distance 0
+    if (A.rs_k > 0 && best_c >= 0) {
+      const int32_t r = random_candidate(L, A, p, best_c);
+      if (best_d != 0 && r != best_c) rc = r;
+    }
+  }
+  if (A.rs_k > 0) {
+    if (tgt) {
+      wsh.rc[tid] = rc;
+      wsh.rd[tid] = best_d - 1u;  // strictly better only (best_d > 0 when rc >= 0)
+    }
+    __syncthreads();
+    for (int e = g; e < TB; e += kGroups) {
+      const int32_t c = wsh.rc[e];
+      if (c >= 0) {
+        const int32_t xy = sh.xy[e];
+        const uint32_t d =
+            group_ssd(L, sh.p[e], xy & 0xFFFF, xy >> 16, sh.t[e], c, lg, wsh.rd[e]);
+        if (lg == 0) wsh.rd[e] = d;
+      }
+    }
+    __syncthreads();
+    if (rc >= 0) {
+      const uint32_t d = wsh.rd[tid];
+      if (d < best_d && L.dsrc[rc]) {
+        best_d = d;
+        best_c = rc;
+      }
+      ne += 1;
+    }
+  }
+  if (active) store_match(L, A, p, stable, cp, inc, best_c, best_d);
   return ne;
 }
 
@@ -617,7 +854,12 @@ __global__ __launch_bounds__(kBlock) void k_pass(DevLevel L, PassArgs A) {
   count_evals(A.evals, ne);
 }
 
-
+template <int TB>
+__global__ __launch_bounds__(kBlock) void k_pass_wide(DevLevel L, PassArgs A) {
+  __shared__ WideShared<TB> sh;
+  const int ne = pass_block_wide<TB>(L, A, xcd_block(blockIdx.x, gridDim.x), sh);
+  count_evals(A.evals, ne);
+}
 
 __global__ void k_copy_targets(const int32_t* tlist, int32_t nS, const int2* src, int2* dst) {
   const int32_t i = blockIdx.x * kBlock + threadIdx.x;
@@ -1437,6 +1679,15 @@ __global__ void k_out_rgb(DevLevel L, uint8_t* out) {
 // ------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------
+// Target lists up to this size take the wide pass (kWideTargets targets per
+// workgroup of kBlock lanes).  Larger ones take the one-lane pass: with its
+// 76 registers six of its workgroups (1536 targets) are resident per compute
+// unit against four of the wide pass's (256 targets), and its early exit
+// costs fewer loads, so once the targets fill the device it is faster
+// (measured crossover between 72 k and 220 k targets).
+static constexpr int32_t kWideMaxTargets = 131072;
+static constexpr int kWideTargets = 64;
+
 static inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
 
 void launch_init_level0(hipStream_t st, const uint8_t* rgb, const uint8_t* mask, DevLevel L0) {
@@ -1487,12 +1738,19 @@ void launch_s0(hipStream_t st, DevLevel L, const PassArgs& A, bool red) {
     k_s0<false, false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
 }
 
-void launch_pass(hipStream_t st, DevLevel L, const PassArgs& A, bool red) {
+bool pass_is_wide(int32_t nS, bool masked, bool red, int32_t wide_max) {
+  return !masked && !red && nS <= (wide_max < 0 ? kWideMaxTargets : wide_max);
+}
+
+void launch_pass(hipStream_t st, DevLevel L, const PassArgs& A, bool red, int32_t wide_max) {
   if (A.nS <= 0) return;
   if (A.excl)
     k_pass<true, false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
   else if (red)
     k_pass<false, true><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
+  else if (pass_is_wide(A.nS, false, false, wide_max))
+    k_pass_wide<kWideTargets>
+        <<<(unsigned)((A.nS + kWideTargets - 1) / kWideTargets), kBlock, 0, st>>>(L, A);
   else
     k_pass<false, false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
 }

@@ -37,6 +37,7 @@ class Params(C.Structure):
         ("seed", C.c_uint64),
         ("temporal_subsample", C.c_int32),
         ("reduce_dims", C.c_int32),
+        ("wide_pass_max", C.c_int32),
     ]
 
 
@@ -113,7 +114,7 @@ class Counters(C.Structure):
     _fields_ = [("nominal_evals", C.c_int64), ("effective_evals", C.c_int64),
                 ("searches", C.c_int64), ("em_iters", C.c_int64), ("recon_pixels", C.c_int64),
                 ("pass_evals", C.c_int64), ("init_evals", C.c_int64),
-                ("onion_evals", C.c_int64)]
+                ("onion_evals", C.c_int64), ("pass_wide_evals", C.c_int64)]
 
 
 class KernelTime(C.Structure):
@@ -121,7 +122,7 @@ class KernelTime(C.Structure):
                 ("ms", C.c_float), ("launches", C.c_int32)]
 
 
-KERNEL_KINDS = {0: "init", 1: "pass", 2: "recon", 3: "other", 4: "onion"}
+KERNEL_KINDS = {0: "init", 1: "pass", 2: "recon", 3: "other", 4: "onion", 5: "pass_wide"}
 
 
 def lib():

@@ -38,11 +38,19 @@ def host(t):
     return t.cpu().numpy()
 
 
-def make_pair(vi, clip, **kw):
-    print(f"[case] {clip.name} {clip.shape} levels={kw.get('levels')}", flush=True)
+def make_pair(vi, clip, wide=-1, **kw):
+    """wide: the library's wide_pass_max (which form its passes take; the
+    results do not depend on it): -1 its own choice, which takes the wide
+    form on these small levels, 0 the one-lane form everywhere."""
+    print(f"[case] {clip.name} {clip.shape} levels={kw.get('levels')} wide={wide}", flush=True)
     o = vio.Oracle(clip.occluded_input(), clip.mask, **kw)
-    g = vi.Clip(dev(clip.occluded_input()), dev(clip.mask), **kw)
+    g = vi.Clip(dev(clip.occluded_input()), dev(clip.mask), wide_pass_max=wide, **kw)
     return o, g
+
+
+# both forms of the search pass (one lane with early exit, or eight lanes per
+# candidate)
+WIDE = [pytest.param(0, id="onelane"), pytest.param(-1, id="wide")]
 
 
 CLIPS = {
@@ -112,9 +120,10 @@ def _forced_state(o, lv, seed):
 
 @pytest.mark.parametrize("name", list(CLIPS))
 @pytest.mark.parametrize("em_iter", [0, 3])
-def test_search_bitexact(vi, name, em_iter):
+@pytest.mark.parametrize("wide", WIDE)
+def test_search_bitexact(vi, name, em_iter, wide):
     clip, L = CLIPS[name]()
-    o, g = make_pair(vi, clip, levels=L, seed=7)
+    o, g = make_pair(vi, clip, wide=wide, levels=L, seed=7)
     for lv in range(L):
         rgbt, cand = _forced_state(o, lv, 100 + lv)
         o.set_state(lv, rgbt=rgbt, cand=cand)
@@ -128,12 +137,13 @@ def test_search_bitexact(vi, name, em_iter):
         assert np.array_equal(on, host(gn)), f"nvox level {lv}"
 
 
-def test_search_variants_bitexact(vi):
+@pytest.mark.parametrize("wide", WIDE)
+def test_search_variants_bitexact(vi, wide):
     # other iteration counts, steps and lambda (odd pass count: state copied back)
     clip, L = CLIPS["small2"]()
     for kw in (dict(pm_iters=3, jf_steps=[1]), dict(pm_iters=4, jf_steps=[]),
                dict(pm_iters=2, jf_steps=[3, 1], lam=0), dict(pm_iters=5, rho=0.7, lam=130)):
-        o, g = make_pair(vi, clip, levels=L, seed=3, **kw)
+        o, g = make_pair(vi, clip, wide=wide, levels=L, seed=3, **kw)
         rgbt, cand = _forced_state(o, 0, 5)
         o.set_state(0, rgbt=rgbt, cand=cand)
         g.set_state(0, rgbt=rgbt, cand=cand)
@@ -209,11 +219,12 @@ def test_transition_bitexact(vi):
 
 
 @pytest.mark.parametrize("name", ["tiny", "small2", "small3", "edge"])
-def test_inpaint_mean_end_to_end_bitexact(vi, name):
+@pytest.mark.parametrize("wide", WIDE)
+def test_inpaint_mean_end_to_end_bitexact(vi, name, wide):
     # MEAN reconstructions are exact in float32 (integer sums, one division),
     # so the whole algorithm is deterministic across implementations
     clip, L = CLIPS[name]()
-    o, g = make_pair(vi, clip, levels=L, seed=12, recon_mode=1)
+    o, g = make_pair(vi, clip, wide=wide, levels=L, seed=12, recon_mode=1)
     a = o.inpaint()
     b = host(g.inpaint())
     assert np.array_equal(a, b)
@@ -322,9 +333,10 @@ def test_temporal_create_matches_oracle(vi):
 
 
 @pytest.mark.parametrize("em_iter", [0, 2])
-def test_temporal_search_bitexact(vi, em_iter):
+@pytest.mark.parametrize("wide", WIDE)
+def test_temporal_search_bitexact(vi, em_iter, wide):
     clip = _temporal_clip()
-    o, g = make_pair(vi, clip, levels=3, seed=7, temporal_subsample=1)
+    o, g = make_pair(vi, clip, wide=wide, levels=3, seed=7, temporal_subsample=1)
     for lv in range(3):
         rgbt, cand = _forced_state(o, lv, 300 + lv)
         o.set_state(lv, rgbt=rgbt, cand=cand)
@@ -390,9 +402,10 @@ P2 = dict(patch=(5, 5, 1))
 
 
 @pytest.mark.parametrize("name", list(IMAGES))
-def test_image_create_and_search_bitexact(vi, name):
+@pytest.mark.parametrize("wide", WIDE)
+def test_image_create_and_search_bitexact(vi, name, wide):
     clip, L = IMAGES[name]()
-    o, g = make_pair(vi, clip, levels=L, seed=7, **P2)
+    o, g = make_pair(vi, clip, wide=wide, levels=L, seed=7, **P2)
     for lv in range(L):
         assert o.info(lv) == g.info(lv)
         for a, b in zip(o.sets(lv), g.sets(lv)):

@@ -61,6 +61,11 @@ def test_random_configuration_mean_inpainting_bitexact(i):
     kw = {k: v for k, v in prm.items() if k != "n_jf"}  # jf_steps sets n_jf
     op = vio.default_params(**kw)
     gp = vi.default_params(**kw)
+    # which form the search passes take (results do not depend on it): the
+    # library's choice, one lane everywhere, or the wide form up to a list
+    # size that splits these clips' levels between the two
+    gp.wide_pass_max = (-1, 0, 600, 4000)[(i // 2) % 4]
+    print(f"    wide_pass_max {gp.wide_pass_max}", flush=True)
     try:
         ref = vio.Oracle(v, m, params=op).inpaint()
     except vio.OracleError as e:
