@@ -136,7 +136,9 @@ def summarize_counters(d):
     return out
 
 
-PASS_KERNEL = "vi::k_pass<false, false>"
+# the exact-distance search pass: one template, instantiated for the passes
+# with the random search fused (every third pass) and for the others
+PASS_KERNELS = ("vi::k_pass<false, false, false>", "vi::k_pass<false, false, true>")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_BYTES = 1 << 30
 SQ_COUNTERS = "SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VMEM_RD SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT GRBM_GUI_ACTIVE"
@@ -150,11 +152,11 @@ def assemble_counters(pass_fetch, pass_write, pass_sq, copy_fetch, copy_write, w
     exactly COPY_BYTES; VALU issue from SQ_INSTS_VALU (wave instructions; a
     CU issues at most one per cycle across its four SIMDs) over the
     dispatch's cycles at 2.4 GHz on 256 CUs."""
-    def load(path, kernel):
-        rows = [r for r in json.load(open(path)) if r["kernel"] == kernel]
+    def load(path, kernels):
+        rows = [r for r in json.load(open(path)) if r["kernel"] in kernels]
         n = sum(r["dispatches"] for r in rows)
         if n == 0:
-            raise SystemExit(f"{path}: no dispatch of {kernel}")
+            raise SystemExit(f"{path}: no dispatch of {kernels}")
         return rows, n
 
     def mean(rows, n, counter):
@@ -162,11 +164,11 @@ def assemble_counters(pass_fetch, pass_write, pass_sq, copy_fetch, copy_write, w
 
     def mean_us(rows, n):
         return sum(r["mean_us"] * r["dispatches"] for r in rows) / n
-    rf, nf = load(pass_fetch, PASS_KERNEL)
-    rw, nw = load(pass_write, PASS_KERNEL)
-    rs, ns = load(pass_sq, PASS_KERNEL)
-    cf_rows, cfn = load(copy_fetch, COPY_KERNEL)
-    cw_rows, cwn = load(copy_write, COPY_KERNEL)
+    rf, nf = load(pass_fetch, PASS_KERNELS)
+    rw, nw = load(pass_write, PASS_KERNELS)
+    rs, ns = load(pass_sq, PASS_KERNELS)
+    cf_rows, cfn = load(copy_fetch, (COPY_KERNEL,))
+    cw_rows, cwn = load(copy_write, (COPY_KERNEL,))
     fk, wk = mean(rf, nf, "FETCH_SIZE"), mean(rw, nw, "WRITE_SIZE")
     cf, cw = mean(cf_rows, cfn, "FETCH_SIZE"), mean(cw_rows, cwn, "WRITE_SIZE")
     fscale = COPY_BYTES / 1024.0 / cf
@@ -175,18 +177,21 @@ def assemble_counters(pass_fetch, pass_write, pass_sq, copy_fetch, copy_write, w
     sq = {c: mean(rs, ns, c) for c in SQ_COUNTERS.split()}
     sq_us = mean_us(rs, ns)
     per_level = []
-    for r in sorted(rf, key=lambda r: -r["grid"]):
-        w = next((x for x in rw if x["grid"] == r["grid"]), None)
-        q = next((x for x in rs if x["grid"] == r["grid"]), None)
+    for r in sorted(rf, key=lambda r: (-r["grid"], r["kernel"])):
+        key = (r["kernel"], r["grid"])
+        w = next((x for x in rw if (x["kernel"], x["grid"]) == key), None)
+        q = next((x for x in rs if (x["kernel"], x["grid"]) == key), None)
         hb = 1024.0 * (r["counters"]["FETCH_SIZE"] * fscale
                        + (w["counters"]["WRITE_SIZE"] * wscale if w else 0.0))
         per_level.append({
-            "grid": r["grid"], "dispatches": r["dispatches"], "mean_us": r["mean_us"],
+            "kernel": r["kernel"], "grid": r["grid"], "dispatches": r["dispatches"],
+            "mean_us": r["mean_us"],
             "hbm_bytes_per_launch": hb, "hbm_gbs": hb / (r["mean_us"] * 1e-6) / 1e9,
             "valu_busy": (q["counters"]["SQ_INSTS_VALU"] / (256 * q["mean_us"] * 2400.0)
                           if q else None)})
     rec = {
-        "kernel": PASS_KERNEL, "workload": workload, "source_sha256": kernel_source_hash(),
+        "kernel": list(PASS_KERNELS), "workload": workload,
+        "source_sha256": kernel_source_hash(),
         "fetch_kib_per_launch": fk, "write_kib_per_launch": wk,
         "fetch_scale": fscale, "write_scale": wscale,
         "hbm_bytes_per_launch": 1024.0 * (fk * fscale + wk * wscale),
@@ -827,7 +832,10 @@ def roofline_of(workload, pass_evals, pass_units, pass_ms, pass_launches, nomina
         "bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": unit,
         "frac": round(achieved / peak, 4),
         "traffic": None if cnt is None else cnt["hbm_bytes_per_launch"],
-        "kernel": "k_pass<false, false> (propagation pass with fused random search, exact distance)",
+        "kernel": "k_pass<false, false, *> (the exact-distance search pass on the levels with "
+                  "more than 131072 targets: <false, false, false> with the random search "
+                  "fused, every third pass; <false, false, true> the other passes, short "
+                  "queues evaluated by lane groups; one template, timed together)",
         "avg_launch_ms": round(avg_ms, 5), "launches": pass_launches,
         "evals_per_launch": round(evals_per_launch, 1),
         "target_passes_per_launch": round(targets_per_launch, 1),

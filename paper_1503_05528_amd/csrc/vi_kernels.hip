@@ -555,12 +555,120 @@ __device__ __forceinline__ void store_match(const DevLevel& L, const PassArgs& A
   }
 }
 
+constexpr int kGrp = 8;
+// Unmasked exact passes without random search over the larger lists: a
+// workgroup of 256 targets whose queue holds at most this many candidates
+// evaluates them with lane groups (two round trips at most) instead of one
+// lane each (up to 13 with early exit); a longer queue keeps one lane each.
+constexpr int32_t kGroupQueueMax = 64;
+
+// Rows of a video patch for the lanes of a group: slot k of lane g holds the
+// row with index 8k + g in the centre-out order of the one-lane distance,
+// coded (dt + 2) | (dy + 2) << 3 in six bits per lane; 63 marks no row.
+constexpr int8_t kCoDt[25] = {0, 0, 0, -1, 1, 0, 0, -1, -1, 1, 1, -2, 2,
+                              -1, -1, 1, 1, -2, -2, 2, 2, -2, -2, 2, 2};
+constexpr int8_t kCoDy[25] = {0, -1, 1, 0, 0, -2, 2, -1, 1, -1, 1, 0, 0,
+                              -2, 2, -2, 2, -1, 1, -1, 1, -2, 2, -2, 2};
+constexpr uint64_t slot_rows(int k) {
+  uint64_t v = 0;
+  for (int g = 0; g < 8; ++g) {
+    const int r = 8 * k + g;
+    const uint64_t code = r < 25 ? (uint64_t)((kCoDt[r] + 2) | ((kCoDy[r] + 2) << 3)) : 63u;
+    v |= code << (6 * g);
+  }
+  return v;
+}
+constexpr uint64_t kSlotRows[4] = {slot_rows(0), slot_rows(1), slot_rows(2), slot_rows(3)};
+
+// Patch distance (unmasked: target voxels outside the volume are not
+// compared) computed by the kGrp lanes of a group.  A video patch: first
+// the eight rows nearest the centre, one per lane, and the 25th row on lane
+// 0; when the group's partial sum already exceeds abort_above the
+// evaluation stops there (the full distance could only be larger, as in the
+// one-lane form), otherwise the 16 other rows follow, two per lane, all
+// loads in flight at once.  An image patch: its five rows on lanes 0-4.  The
+// lanes' sums are added with DPP within each group of eight lanes (quad
+// swaps, then the half-row mirror), modulo 2^32 like the one-lane sum, so
+// the full distance is the same.  Returns the full distance when it is
+// <= abort_above, otherwise some value above it.  Every lane of the group
+// must call it together with the same arguments.
+__device__ __forceinline__ uint32_t group_sum8(uint32_t d) {
+  d += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)d, 0xB1, 0xF, 0xF, false);   // [1,0,3,2]
+  d += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)d, 0x4E, 0xF, 0xF, false);   // [2,3,0,1]
+  d += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)d, 0x141, 0xF, 0xF, false);  // half mirror
+  return d;
+}
+
+// the group's sum over the rows of slots SA and SB (SB < 0: none) of lane lg;
+// a slot without a row on this lane loads nothing and adds nothing
+template <int SA, int SB>
+__device__ __forceinline__ uint32_t group_rows(const DevLevel& L, int32_t p, int32_t py,
+                                               int32_t pt, int32_t c, int lg, uint32_t xm,
+                                               bool vid) {
+  constexpr int NS = SB < 0 ? 1 : 2;
+  const uint2* __restrict__ vox = L.vox;
+  Row5 a[NS], b[NS];
+  uint32_t okm[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const int k = i == 0 ? SA : SB;
+    int dt, dy;
+    bool rv;
+    if (vid) {
+      const uint32_t code = (uint32_t)(kSlotRows[k] >> (6 * lg)) & 63u;
+      rv = code != 63u;
+      dt = rv ? (int)(code & 7u) - 2 : 0;
+      dy = rv ? (int)(code >> 3) - 2 : 0;
+    } else {
+      rv = k == 0 && lg < 5;
+      dt = 0;
+      dy = rv ? lg - 2 : 0;
+    }
+    const int32_t tt = pt + dt, yy = py + dy;
+    const bool rok = rv && tt >= 0 && tt < L.T && yy >= 0 && yy < L.H;
+    const int32_t row = dt * L.WH + dy * L.W;
+    okm[i] = rok ? xm : 0u;
+    if (rv) {
+      // the video holds two voxels of padding on both sides; a target row
+      // outside the volume reads the centre row and is masked
+      b[i] = load_row5(vox + (c + row - 2));
+      a[i] = load_row5(vox + ((rok ? p + row : p) - 2));
+    } else {
+#pragma unroll
+      for (int x = 0; x < 5; ++x) a[i].v[x] = b[i].v[x] = make_uint2(0, 0);
+    }
+  }
+  SsdAcc q{0u, 0u, 0};
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+#pragma unroll
+    for (int x = 0; x < 5; ++x) {
+      const bool ok = (okm[i] >> x) & 1u;
+      acc_voxel(q, ok ? a[i].v[x] : make_uint2(0, 0), ok ? b[i].v[x] : make_uint2(0, 0));
+    }
+  }
+  return group_sum8(q.sc + (uint32_t)L.lambda * q.st);
+}
+
+__device__ __forceinline__ uint32_t group_ssd(const DevLevel& L, int32_t p, int32_t px, int32_t py,
+                                              int32_t pt, int32_t c, int lg,
+                                              uint32_t abort_above) {
+  const bool vid = L.ht != 0;
+  const int klo = px < 2 ? 2 - px : 0;
+  const int khi = px + 2 >= L.W ? L.W + 1 - px : 4;
+  const uint32_t xm = (0x1fu << klo) & (0x1fu >> (4 - khi));
+  const uint32_t d0 = group_rows<0, 3>(L, p, py, pt, c, lg, xm, vid);
+  if (!vid || d0 > abort_above) return d0;
+  return d0 + group_rows<1, 2>(L, p, py, pt, c, lg, xm, true);
+}
+
 // One block of BLK consecutive targets (block index blk of the target list);
 // returns the evaluations this thread accounts for.  All threads of the
 // workgroup must call it together.
-template <int BLK, bool MASKED, bool RED = false>
+template <int BLK, bool MASKED, bool RED = false, bool GQ = false>
 __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, int32_t blk,
                                           PassShared<BLK>& sh) {
+  static_assert(!GQ || (!MASKED && !RED), "group evaluation: unmasked exact distances");
   int32_t* s_p = sh.p;
   int32_t* s_xy = sh.xy;
   int32_t* s_t = sh.t;
@@ -593,6 +701,20 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
                               cp);
     __syncthreads();
     const int32_t nq = s_nq;
+    if (GQ && nq <= kGroupQueueMax) {
+      // a short queue: one group of kGrp lanes per candidate
+      const int g = tid / kGrp, lg = tid % kGrp;
+      for (int32_t e = g; e < nq; e += BLK / kGrp) {
+        const uint32_t ent = s_q[e];
+        const int lt = ent & 255, j = ent >> 8;
+        const int32_t xy = s_xy[lt];
+        const uint32_t bound = (uint32_t)(s_best[lt] >> 3);
+        const uint32_t d = group_ssd(L, s_p[lt], xy & 0xFFFF, xy >> 16, s_t[lt],
+                                     s_cand[lt * 6 + j], lg, bound);
+        if (lg == 0 && d <= bound)
+          atomicMin(&s_best[lt], ((unsigned long long)d << 3) | (unsigned long long)(j + 1));
+      }
+    } else
     for (int32_t e = tid; e < nq; e += BLK) {
       const uint32_t ent = s_q[e];
       const int lt = ent & 255, j = ent >> 8;
@@ -653,98 +775,6 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
 // distance instead of a partial sum above the bound: the same candidates win
 // with the same distances, and the same evaluations are counted.
 // ------------------------------------------------------------------------
-constexpr int kGrp = 8;
-
-// Rows of a video patch for the lanes of a group: slot k of lane g holds the
-// row with index 8k + g in the centre-out order of the one-lane distance,
-// coded (dt + 2) | (dy + 2) << 3 in six bits per lane; 63 marks no row.
-constexpr int8_t kCoDt[25] = {0, 0, 0, -1, 1, 0, 0, -1, -1, 1, 1, -2, 2,
-                              -1, -1, 1, 1, -2, -2, 2, 2, -2, -2, 2, 2};
-constexpr int8_t kCoDy[25] = {0, -1, 1, 0, 0, -2, 2, -1, 1, -1, 1, 0, 0,
-                              -2, 2, -2, 2, -1, 1, -1, 1, -2, 2, -2, 2};
-constexpr uint64_t slot_rows(int k) {
-  uint64_t v = 0;
-  for (int g = 0; g < 8; ++g) {
-    const int r = 8 * k + g;
-    const uint64_t code = r < 25 ? (uint64_t)((kCoDt[r] + 2) | ((kCoDy[r] + 2) << 3)) : 63u;
-    v |= code << (6 * g);
-  }
-  return v;
-}
-constexpr uint64_t kSlotRows[4] = {slot_rows(0), slot_rows(1), slot_rows(2), slot_rows(3)};
-
-// Patch distance (unmasked: target voxels outside the volume are not
-// compared) computed by the kGrp lanes of a group.  A video patch: first the
-// eight rows nearest the centre, one per lane; when the group's partial sum
-// already exceeds abort_above the evaluation stops there (the full distance
-// could only be larger, as in the one-lane form), otherwise the 17 other rows
-// follow, up to three per lane, all loads in flight at once.  An image patch:
-// its five rows on lanes 0-4.  The lanes' sums are added with DPP within
-// each group of eight lanes (quad swaps, then the half-row mirror), modulo
-// 2^32 like the one-lane sum, so the full distance is the same.  Returns the
-// full distance when it is <= abort_above, otherwise some value above it.
-// Every lane of the group must call it together with the same arguments.
-__device__ __forceinline__ uint32_t group_sum8(uint32_t d) {
-  d += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)d, 0xB1, 0xF, 0xF, false);   // [1,0,3,2]
-  d += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)d, 0x4E, 0xF, 0xF, false);   // [2,3,0,1]
-  d += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)d, 0x141, 0xF, 0xF, false);  // half mirror
-  return d;
-}
-
-template <int K0, int K1>
-__device__ __forceinline__ uint32_t group_rows(const DevLevel& L, int32_t p, int32_t py,
-                                               int32_t pt, int32_t c, int lg, uint32_t xm,
-                                               bool vid) {
-  const uint2* __restrict__ vox = L.vox;
-  Row5 a[K1 - K0], b[K1 - K0];
-  uint32_t okm[K1 - K0];
-#pragma unroll
-  for (int k = K0; k < K1; ++k) {
-    int dt, dy;
-    bool rv;
-    if (vid) {
-      const uint32_t code = (uint32_t)(kSlotRows[k] >> (6 * lg)) & 63u;
-      rv = code != 63u;
-      dt = rv ? (int)(code & 7u) - 2 : 0;
-      dy = rv ? (int)(code >> 3) - 2 : 0;
-    } else {
-      rv = lg < 5;
-      dt = 0;
-      dy = rv ? lg - 2 : 0;
-    }
-    const int32_t tt = pt + dt, yy = py + dy;
-    const bool rok = rv && tt >= 0 && tt < L.T && yy >= 0 && yy < L.H;
-    const int32_t row = dt * L.WH + dy * L.W;
-    okm[k - K0] = rok ? xm : 0u;
-    // no row: the centre rows (in the volume), masked; the video holds two
-    // voxels of padding on both sides
-    b[k - K0] = load_row5(vox + (c + row - 2));
-    a[k - K0] = load_row5(vox + ((rok ? p + row : p) - 2));
-  }
-  SsdAcc q{0u, 0u, 0};
-#pragma unroll
-  for (int k = 0; k < K1 - K0; ++k) {
-#pragma unroll
-    for (int x = 0; x < 5; ++x) {
-      const bool ok = (okm[k] >> x) & 1u;
-      acc_voxel(q, ok ? a[k].v[x] : make_uint2(0, 0), ok ? b[k].v[x] : make_uint2(0, 0));
-    }
-  }
-  return group_sum8(q.sc + (uint32_t)L.lambda * q.st);
-}
-
-__device__ __forceinline__ uint32_t group_ssd(const DevLevel& L, int32_t p, int32_t px, int32_t py,
-                                              int32_t pt, int32_t c, int lg,
-                                              uint32_t abort_above) {
-  const bool vid = L.ht != 0;
-  const int klo = px < 2 ? 2 - px : 0;
-  const int khi = px + 2 >= L.W ? L.W + 1 - px : 4;
-  const uint32_t xm = (0x1fu << klo) & (0x1fu >> (4 - khi));
-  const uint32_t d0 = group_rows<0, 1>(L, p, py, pt, c, lg, xm, vid);
-  if (!vid || d0 > abort_above) return d0;
-  return d0 + group_rows<1, 4>(L, p, py, pt, c, lg, xm, true);
-}
-
 template <int TB>
 struct WideShared {
   PassShared<TB> s;
@@ -847,10 +877,13 @@ __device__ __forceinline__ int pass_block_wide(const DevLevel& L, const PassArgs
   return ne;
 }
 
-template <bool MASKED, bool RED>
+// GQ: short queues evaluated by lane groups (the unmasked exact passes
+// without random search; a separate instantiation, so that the passes with
+// random search keep the one-lane form's 76 registers and six waves per SIMD)
+template <bool MASKED, bool RED, bool GQ>
 __global__ __launch_bounds__(kBlock) void k_pass(DevLevel L, PassArgs A) {
   __shared__ PassShared<kBlock> sh;
-  const int ne = pass_block<kBlock, MASKED, RED>(L, A, xcd_block(blockIdx.x, gridDim.x), sh);
+  const int ne = pass_block<kBlock, MASKED, RED, GQ>(L, A, xcd_block(blockIdx.x, gridDim.x), sh);
   count_evals(A.evals, ne);
 }
 
@@ -1745,14 +1778,16 @@ bool pass_is_wide(int32_t nS, bool masked, bool red, int32_t wide_max) {
 void launch_pass(hipStream_t st, DevLevel L, const PassArgs& A, bool red, int32_t wide_max) {
   if (A.nS <= 0) return;
   if (A.excl)
-    k_pass<true, false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
+    k_pass<true, false, false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
   else if (red)
-    k_pass<false, true><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
+    k_pass<false, true, false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
   else if (pass_is_wide(A.nS, false, false, wide_max))
     k_pass_wide<kWideTargets>
         <<<(unsigned)((A.nS + kWideTargets - 1) / kWideTargets), kBlock, 0, st>>>(L, A);
+  else if (A.rs_k == 0)
+    k_pass<false, false, true><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
   else
-    k_pass<false, false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
+    k_pass<false, false, false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
 }
 
 void launch_rerank(hipStream_t st, DevLevel L, const int32_t* tlist, int32_t nS) {
