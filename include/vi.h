@@ -87,10 +87,11 @@ typedef struct {
                            compare those features (vi_set_reduction) */
   int32_t wide_pass_max; /* execution only, results do not depend on it:
                             -1 (default) lets the library choose; otherwise
-                            the unmasked exact passes over at most this many
-                            targets compute each candidate's distance with
-                            eight lanes (every row load at once) instead of
-                            one lane with early exit (0: never) */
+                            the exact passes (the onion peel's included) over
+                            at most this many targets compute each
+                            candidate's distance with a group of eight lanes
+                            (two round trips at most) instead of one lane
+                            with early exit (0: never) */
 } vi_params;
 
 typedef struct vi_ctx vi_ctx; /* one clip: all its device state */

@@ -283,7 +283,7 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
   const bool red = d.rd > 0 && !excl;
   // onion searches (masked) count apart from the EM loop's, and the EM
   // loop's passes of the wide form apart from the one-lane form's
-  const bool wide = vi::pass_is_wide(nS, excl != nullptr, red, c->prm.wide_pass_max);
+  const bool wide = vi::pass_is_wide(nS, red, c->prm.wide_pass_max);
   unsigned long long* ev_pass = c->d_cnt + (size_t)(excl ? 3 : (wide ? 4 : 1)) * vi::kCntWords;
   unsigned long long* ev_init = c->d_cnt + (size_t)(excl ? 3 : 2) * vi::kCntWords;
   A.evals = ev_init;

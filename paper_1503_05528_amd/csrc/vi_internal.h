@@ -168,9 +168,9 @@ void launch_fill_u64(hipStream_t st, unsigned long long* p, int32_t n);
 // features); launch_rerank then evaluates every target's match exactly
 void launch_s0(hipStream_t st, DevLevel L, const PassArgs& A, bool red = false);
 // Whether launch_pass takes the wide form for a target list of nS targets:
-// unmasked exact passes over at most wide_max targets (-1: the library's
-// limit).
-bool pass_is_wide(int32_t nS, bool masked, bool red, int32_t wide_max);
+// exact passes (also the onion peel's masked ones) over at most wide_max
+// targets (-1: the library's limit).
+bool pass_is_wide(int32_t nS, bool red, int32_t wide_max);
 void launch_pass(hipStream_t st, DevLevel L, const PassArgs& A, bool red = false,
                  int32_t wide_max = -1);
 void launch_rerank(hipStream_t st, DevLevel L, const int32_t* tlist, int32_t nS);

@@ -580,8 +580,9 @@ constexpr uint64_t slot_rows(int k) {
 }
 constexpr uint64_t kSlotRows[4] = {slot_rows(0), slot_rows(1), slot_rows(2), slot_rows(3)};
 
-// Patch distance (unmasked: target voxels outside the volume are not
-// compared) computed by the kGrp lanes of a group.  A video patch: first
+// Patch distance computed by the kGrp lanes of a group (target voxels
+// outside the volume, or flagged in excl when MASKED, are not compared; the
+// candidate patch is a source, inside the volume).  A video patch: first
 // the eight rows nearest the centre, one per lane, and the 25th row on lane
 // 0; when the group's partial sum already exceeds abort_above the
 // evaluation stops there (the full distance could only be larger, as in the
@@ -601,10 +602,10 @@ __device__ __forceinline__ uint32_t group_sum8(uint32_t d) {
 
 // the group's sum over the rows of slots SA and SB (SB < 0: none) of lane lg;
 // a slot without a row on this lane loads nothing and adds nothing
-template <int SA, int SB>
-__device__ __forceinline__ uint32_t group_rows(const DevLevel& L, int32_t p, int32_t py,
-                                               int32_t pt, int32_t c, int lg, uint32_t xm,
-                                               bool vid) {
+template <int SA, int SB, bool MASKED>
+__device__ __forceinline__ uint32_t group_rows(const DevLevel& L, const uint8_t* __restrict__ excl,
+                                               int32_t p, int32_t py, int32_t pt, int32_t c,
+                                               int lg, uint32_t xm, bool vid) {
   constexpr int NS = SB < 0 ? 1 : 2;
   const uint2* __restrict__ vox = L.vox;
   Row5 a[NS], b[NS];
@@ -631,8 +632,19 @@ __device__ __forceinline__ uint32_t group_rows(const DevLevel& L, int32_t p, int
     if (rv) {
       // the video holds two voxels of padding on both sides; a target row
       // outside the volume reads the centre row and is masked
+      const int32_t base = (rok ? p + row : p) - 2;
       b[i] = load_row5(vox + (c + row - 2));
-      a[i] = load_row5(vox + ((rok ? p + row : p) - 2));
+      a[i] = load_row5(vox + base);
+      if (MASKED) {
+        // the row's five exclusion bytes with one 8-byte load (the masks
+        // hold 16 bytes of padding on both sides)
+        const int32_t al = base & ~3;
+        const u32x2_a4 e = *reinterpret_cast<const u32x2_a4*>(excl + al);
+        const uint64_t e64 = ((uint64_t)e[1] << 32 | e[0]) >> (8 * (base - al));
+#pragma unroll
+        for (int x = 0; x < 5; ++x)
+          if ((e64 >> (8 * x)) & 0xffu) okm[i] &= ~(1u << x);
+      }
     } else {
 #pragma unroll
       for (int x = 0; x < 5; ++x) a[i].v[x] = b[i].v[x] = make_uint2(0, 0);
@@ -650,16 +662,17 @@ __device__ __forceinline__ uint32_t group_rows(const DevLevel& L, int32_t p, int
   return group_sum8(q.sc + (uint32_t)L.lambda * q.st);
 }
 
-__device__ __forceinline__ uint32_t group_ssd(const DevLevel& L, int32_t p, int32_t px, int32_t py,
-                                              int32_t pt, int32_t c, int lg,
-                                              uint32_t abort_above) {
+template <bool MASKED>
+__device__ __forceinline__ uint32_t group_ssd(const DevLevel& L, const uint8_t* excl, int32_t p,
+                                              int32_t px, int32_t py, int32_t pt, int32_t c,
+                                              int lg, uint32_t abort_above) {
   const bool vid = L.ht != 0;
   const int klo = px < 2 ? 2 - px : 0;
   const int khi = px + 2 >= L.W ? L.W + 1 - px : 4;
   const uint32_t xm = (0x1fu << klo) & (0x1fu >> (4 - khi));
-  const uint32_t d0 = group_rows<0, 3>(L, p, py, pt, c, lg, xm, vid);
+  const uint32_t d0 = group_rows<0, 3, MASKED>(L, excl, p, py, pt, c, lg, xm, vid);
   if (!vid || d0 > abort_above) return d0;
-  return d0 + group_rows<1, 2>(L, p, py, pt, c, lg, xm, true);
+  return d0 + group_rows<1, 2, MASKED>(L, excl, p, py, pt, c, lg, xm, true);
 }
 
 // One block of BLK consecutive targets (block index blk of the target list);
@@ -709,8 +722,8 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
         const int lt = ent & 255, j = ent >> 8;
         const int32_t xy = s_xy[lt];
         const uint32_t bound = (uint32_t)(s_best[lt] >> 3);
-        const uint32_t d = group_ssd(L, s_p[lt], xy & 0xFFFF, xy >> 16, s_t[lt],
-                                     s_cand[lt * 6 + j], lg, bound);
+        const uint32_t d = group_ssd<false>(L, nullptr, s_p[lt], xy & 0xFFFF, xy >> 16,
+                                            s_t[lt], s_cand[lt * 6 + j], lg, bound);
         if (lg == 0 && d <= bound)
           atomicMin(&s_best[lt], ((unsigned long long)d << 3) | (unsigned long long)(j + 1));
       }
@@ -768,12 +781,12 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
 // targets leaves most compute units idle and a pass takes as long as the
 // longest chain of dependent fetches in a wave: a queued candidate with early
 // exit is up to 13 round trips, its random-search candidate 13 more.  Here a
-// group of kGrp lanes computes one candidate's full distance with every row
-// load in flight at once (one round trip), for the queued candidates and
-// then for the random-search candidates, and a workgroup of 256 lanes serves
-// TB targets.  Without early exit a losing candidate's distance is its full
-// distance instead of a partial sum above the bound: the same candidates win
-// with the same distances, and the same evaluations are counted.
+// group of kGrp lanes computes one candidate's distance (group_ssd: two
+// round trips at most), for the queued candidates and then for the
+// random-search candidates, and a workgroup of 256 lanes serves TB targets.
+// The same candidates win with the same distances, and the same evaluations
+// are counted.  MASKED: the onion peel's passes (target set and exclusions
+// as in the one-lane form).
 // ------------------------------------------------------------------------
 template <int TB>
 struct WideShared {
@@ -782,9 +795,9 @@ struct WideShared {
   uint32_t rd[TB];  // its distance
 };
 
-// One block of TB consecutive targets with NT = kBlock lanes (unmasked exact
+// One block of TB consecutive targets with NT = kBlock lanes (exact
 // distance); returns the evaluations this thread accounts for.
-template <int TB>
+template <int TB, bool MASKED>
 __device__ __forceinline__ int pass_block_wide(const DevLevel& L, const PassArgs& A, int32_t blk,
                                                WideShared<TB>& wsh) {
   static_assert(TB % 64 == 0 && TB <= kBlock, "targets per workgroup: whole waves");
@@ -815,8 +828,8 @@ __device__ __forceinline__ int pass_block_wide(const DevLevel& L, const PassArgs
   uint16_t cp = 0;
   if (A.s > 0) {
     if (tgt)
-      gather_candidates<false>(L, A, active, p, px, py, pt, inc, tid, sh.cand, sh.q, sh.nq,
-                               stable, cp);
+      gather_candidates<MASKED>(L, A, active, p, px, py, pt, inc, tid, sh.cand, sh.q, sh.nq,
+                                stable, cp);
     __syncthreads();
     const int32_t nq = sh.nq;
     for (int32_t e = g; e < nq; e += kGroups) {
@@ -825,8 +838,8 @@ __device__ __forceinline__ int pass_block_wide(const DevLevel& L, const PassArgs
       const int32_t xy = sh.xy[lt];
       // a candidate whose partial distance exceeds the current best cannot win
       const uint32_t bound = (uint32_t)(sh.best[lt] >> 3);
-      const uint32_t d = group_ssd(L, sh.p[lt], xy & 0xFFFF, xy >> 16, sh.t[lt],
-                                   sh.cand[lt * 6 + j], lg, bound);
+      const uint32_t d = group_ssd<MASKED>(L, A.excl, sh.p[lt], xy & 0xFFFF, xy >> 16,
+                                           sh.t[lt], sh.cand[lt * 6 + j], lg, bound);
       if (lg == 0 && d <= bound)
         atomicMin(&sh.best[lt], ((unsigned long long)d << 3) | (unsigned long long)(j + 1));
     }
@@ -859,7 +872,8 @@ __device__ __forceinline__ int pass_block_wide(const DevLevel& L, const PassArgs
       if (c >= 0) {
         const int32_t xy = sh.xy[e];
         const uint32_t d =
-            group_ssd(L, sh.p[e], xy & 0xFFFF, xy >> 16, sh.t[e], c, lg, wsh.rd[e]);
+            group_ssd<MASKED>(L, A.excl, sh.p[e], xy & 0xFFFF, xy >> 16, sh.t[e], c, lg,
+                              wsh.rd[e]);
         if (lg == 0) wsh.rd[e] = d;
       }
     }
@@ -887,10 +901,10 @@ __global__ __launch_bounds__(kBlock) void k_pass(DevLevel L, PassArgs A) {
   count_evals(A.evals, ne);
 }
 
-template <int TB>
+template <int TB, bool MASKED>
 __global__ __launch_bounds__(kBlock) void k_pass_wide(DevLevel L, PassArgs A) {
   __shared__ WideShared<TB> sh;
-  const int ne = pass_block_wide<TB>(L, A, xcd_block(blockIdx.x, gridDim.x), sh);
+  const int ne = pass_block_wide<TB, MASKED>(L, A, xcd_block(blockIdx.x, gridDim.x), sh);
   count_evals(A.evals, ne);
 }
 
@@ -1771,19 +1785,21 @@ void launch_s0(hipStream_t st, DevLevel L, const PassArgs& A, bool red) {
     k_s0<false, false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
 }
 
-bool pass_is_wide(int32_t nS, bool masked, bool red, int32_t wide_max) {
-  return !masked && !red && nS <= (wide_max < 0 ? kWideMaxTargets : wide_max);
+bool pass_is_wide(int32_t nS, bool red, int32_t wide_max) {
+  return !red && nS <= (wide_max < 0 ? kWideMaxTargets : wide_max);
 }
 
 void launch_pass(hipStream_t st, DevLevel L, const PassArgs& A, bool red, int32_t wide_max) {
   if (A.nS <= 0) return;
-  if (A.excl)
+  const unsigned wide_grid = (unsigned)((A.nS + kWideTargets - 1) / kWideTargets);
+  if (A.excl && pass_is_wide(A.nS, false, wide_max))
+    k_pass_wide<kWideTargets, true><<<wide_grid, kBlock, 0, st>>>(L, A);
+  else if (A.excl)
     k_pass<true, false, false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
   else if (red)
     k_pass<false, true, false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
-  else if (pass_is_wide(A.nS, false, false, wide_max))
-    k_pass_wide<kWideTargets>
-        <<<(unsigned)((A.nS + kWideTargets - 1) / kWideTargets), kBlock, 0, st>>>(L, A);
+  else if (pass_is_wide(A.nS, false, wide_max))
+    k_pass_wide<kWideTargets, false><<<wide_grid, kBlock, 0, st>>>(L, A);
   else if (A.rs_k == 0)
     k_pass<false, false, true><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
   else

@@ -182,9 +182,10 @@ def test_reconstruct_parity(vi, name, mode):
 # "edge": masked distances whose rows start before the first voxel or end
 # after the last one of the volume
 @pytest.mark.parametrize("name", ["tiny", "small2", "small3", "edge"])
-def test_onion_mean_bitexact(vi, name):
+@pytest.mark.parametrize("wide", WIDE)
+def test_onion_mean_bitexact(vi, name, wide):
     clip, L = CLIPS[name]()
-    o, g = make_pair(vi, clip, levels=L, seed=4, recon_mode=1)
+    o, g = make_pair(vi, clip, wide=wide, levels=L, seed=4, recon_mode=1)
     assert o.onion_init() == g.onion_init()
     for a, b in zip(o.get_state(L - 1), g.get_state(L - 1)):
         assert np.array_equal(a, host(b))
@@ -278,12 +279,13 @@ def test_errors(vi):
 
 @pytest.mark.parametrize("name", ["tiny", "small2", "small3", "edge"])
 @pytest.mark.parametrize("mode", [0, 1])
-def test_onion_layers_teacher_forced(vi, name, mode):
+@pytest.mark.parametrize("wide", WIDE)
+def test_onion_layers_teacher_forced(vi, name, mode, wide):
     # the peel one layer at a time, each layer started from the oracle's
     # state: the layer (erosion), the masked search of its targets and the
     # reconstruction from contributors outside H' (Eqs. (3.10)-(3.11))
     clip, L = CLIPS[name]()
-    o, g = make_pair(vi, clip, levels=L, seed=4, recon_mode=mode)
+    o, g = make_pair(vi, clip, wide=wide, levels=L, seed=4, recon_mode=mode)
     lv = L - 1
     Hp = o.sets(lv)[0].copy()
     gHp = dev(Hp)
