@@ -558,8 +558,9 @@ __device__ __forceinline__ void store_match(const DevLevel& L, const PassArgs& A
 constexpr int kGrp = 8;
 // Unmasked exact passes without random search over the larger lists: a
 // workgroup of 256 targets whose queue holds at most this many candidates
-// evaluates them with lane groups (two round trips at most) instead of one
-// lane each (up to 13 with early exit); a longer queue keeps one lane each.
+// (in proportion for smaller workgroups) evaluates them with lane groups
+// (two round trips at most) instead of one lane each (up to 13 with early
+// exit); a longer queue keeps one lane each.
 constexpr int32_t kGroupQueueMax = 64;
 
 // Rows of a video patch for the lanes of a group: slot k of lane g holds the
@@ -714,7 +715,7 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
                               cp);
     __syncthreads();
     const int32_t nq = s_nq;
-    if (GQ && nq <= kGroupQueueMax) {
+    if (GQ && nq <= kGroupQueueMax * BLK / kBlock) {
       // a short queue: one group of kGrp lanes per candidate
       const int g = tid / kGrp, lg = tid % kGrp;
       for (int32_t e = g; e < nq; e += BLK / kGrp) {
@@ -1352,7 +1353,7 @@ __global__ __launch_bounds__(BLK) void kb_s0(BatchArgs B, int32_t slot) {
 }
 
 // one chunk of a batched pass (every thread of the workgroup calls it)
-template <int BLK, bool MASKED>
+template <int BLK, bool MASKED, bool GQ>
 __device__ __forceinline__ void kb_pass_chunk(const BatchArgs& B, PassShared<BLK>& sh, int32_t c,
                                               int32_t s, int32_t k, int32_t parity, int32_t t,
                                               int32_t since) {
@@ -1371,7 +1372,7 @@ __device__ __forceinline__ void kb_pass_chunk(const BatchArgs& B, PassShared<BLK
   A.t = t;
   A.since = since;
   A.step = uniform(J.step);
-  const int ne = pass_block<BLK, MASKED>(L, A, c - uniform(J.tchunk0), sh);
+  const int ne = pass_block<BLK, MASKED, false, GQ>(L, A, c - uniform(J.tchunk0), sh);
   count_evals(uniform(J.evals), ne);
 }
 
@@ -1379,17 +1380,19 @@ __device__ __forceinline__ void kb_pass_chunk(const BatchArgs& B, PassShared<BLK
 // (direct launches, grid = the chunk count) workgroup b takes chunk
 // xcd_block(b) and nothing else: without a loop around the pass the kernel
 // keeps the register count, and so the occupancy, of the single-clip pass.
-template <int BLK, bool MASKED, bool PERSIST>
+// GQ: the passes without random search (k = 0), short queues evaluated by
+// lane groups, as the single-clip pass does
+template <int BLK, bool MASKED, bool PERSIST, bool GQ>
 __global__ __launch_bounds__(BLK) void kb_pass(BatchArgs B, int32_t s, int32_t k, int32_t parity,
                                                int32_t slot, int32_t t, int32_t since) {
   __shared__ PassShared<BLK> sh;
   const int32_t n = B.counts[0];
   if (PERSIST) {
     FOR_EACH_CHUNK(B.queue + slot, n, false, c)
-        kb_pass_chunk<BLK, MASKED>(B, sh, c, s, k, parity, t, since);
+        kb_pass_chunk<BLK, MASKED, GQ>(B, sh, c, s, k, parity, t, since);
   } else {
     const int32_t c = xcd_block(blockIdx.x, gridDim.x);
-    if (c < n) kb_pass_chunk<BLK, MASKED>(B, sh, c, s, k, parity, t, since);
+    if (c < n) kb_pass_chunk<BLK, MASKED, GQ>(B, sh, c, s, k, parity, t, since);
   }
 }
 
@@ -2031,12 +2034,22 @@ template <bool M, bool P>
 static void batch_pass_shape(hipStream_t st, const BatchArgs& B, int blk, int32_t grid,
                              int32_t s, int32_t k, int32_t parity, int32_t slot, int32_t t,
                              int32_t since) {
-  if (blk == 64)
-    kb_pass<64, M, P><<<grid, 64, 0, st>>>(B, s, k, parity, slot, t, since);
-  else if (blk == 128)
-    kb_pass<128, M, P><<<grid, 128, 0, st>>>(B, s, k, parity, slot, t, since);
-  else
-    kb_pass<256, M, P><<<grid, 256, 0, st>>>(B, s, k, parity, slot, t, since);
+  // unmasked passes without random search: the group-queue form
+  constexpr bool G = !M;
+  if (G && k == 0) {
+    if (blk == 64)
+      kb_pass<64, M, P, G><<<grid, 64, 0, st>>>(B, s, k, parity, slot, t, since);
+    else if (blk == 128)
+      kb_pass<128, M, P, G><<<grid, 128, 0, st>>>(B, s, k, parity, slot, t, since);
+    else
+      kb_pass<256, M, P, G><<<grid, 256, 0, st>>>(B, s, k, parity, slot, t, since);
+  } else if (blk == 64) {
+    kb_pass<64, M, P, false><<<grid, 64, 0, st>>>(B, s, k, parity, slot, t, since);
+  } else if (blk == 128) {
+    kb_pass<128, M, P, false><<<grid, 128, 0, st>>>(B, s, k, parity, slot, t, since);
+  } else {
+    kb_pass<256, M, P, false><<<grid, 256, 0, st>>>(B, s, k, parity, slot, t, since);
+  }
 }
 
 template <bool M>
