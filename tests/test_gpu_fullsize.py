@@ -124,6 +124,57 @@ def test_hd_full_level_bitexact(vi):
     check_full_level(vi, "hd", synth.hd())
 
 
+def forced_state(o, lv, seed):
+    """Random matches on the level's targets (every seventh unset) over a
+    randomly filled hole."""
+    rgbt, cand0, _, _ = o.get_state(lv)
+    rgbt = rgbt.copy()
+    hole, dsrc, htil = o.sets(lv)
+    rng = np.random.default_rng(seed)
+    src = np.flatnonzero(dsrc.ravel())
+    tg = np.flatnonzero(htil.ravel())
+    cand = np.full(cand0.shape, -1, np.int32)
+    cand.ravel()[tg] = src[rng.integers(0, len(src), len(tg))]
+    cand.ravel()[tg[::7]] = -1
+    hv = hole.ravel() == 1
+    rgbt.reshape(-1, 5)[hv] = rng.integers(0, 256, (int(hv.sum()), 5), dtype=np.uint8)
+    return rgbt, cand
+
+
+@pytest.mark.timeout(900)
+def test_hd_coarse_levels_bitexact(vi):
+    """The HD clip's coarse levels at their full size: teacher-forced
+    searches of levels 4 and 3 (at most 131 072 targets: the wide pass) and
+    of level 2 (the one-lane pass, short queues by lane groups) compared
+    array for array, and the onion peel of the coarsest level (its masked
+    passes in the wide form) in MEAN mode, bit for bit."""
+    prm = dict(PARAMS["hd"], recon_mode=1)
+    clip = synth.hd()
+    video, mask = clip.occluded_input(), clip.mask
+    print("[case] hd coarse levels: oracle set-up", flush=True)
+    o = vio.Oracle(video, mask, **prm)
+    g = vi.Clip(dev(video), dev(mask), **prm)
+    assert o.onion_init() == g.onion_init()
+    for a, b in zip(o.get_state(4), g.get_state(4)):
+        assert np.array_equal(a, host(b)), "onion peel of level 4"
+    print("[case] hd coarse levels: onion peel identical", flush=True)
+    for lv in (4, 3, 2):
+        targets = o.info(lv)[1][1]
+        rgbt, cand = forced_state(o, lv, 40 + lv)
+        o.set_state(lv, rgbt=rgbt, cand=cand)
+        g.set_state(lv, rgbt=rgbt, cand=cand)
+        o.nnf_search(lv, 3)
+        g.nnf_search(lv, 3)
+        _, oc, od, on = o.get_state(lv)
+        _, gc, gd, gn = (host(t) for t in g.get_state(lv))
+        assert np.array_equal(oc, gc), f"level {lv}: {np.count_nonzero(oc != gc)} matches differ"
+        assert np.array_equal(od, gd), f"level {lv}: {np.count_nonzero(od != gd)} distances differ"
+        assert np.array_equal(on, gn), f"level {lv}: voxel counts differ"
+        print(f"[case] hd level {lv} ({targets} targets): search identical", flush=True)
+    g.close()
+    o.close()
+
+
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("W,H,levels", [(1920, 1080, 5), (3840, 2160, 6)])
 def test_image_full_level_bitexact(vi, W, H, levels):
