@@ -297,7 +297,7 @@ vi_status search(vi_ctx* c, int32_t level, const int32_t* tlist, int32_t nS,
     VI_TRY(launched("features"));
   }
   r = prof_begin(c, VI_K_INIT);
-  vi::launch_s0(c->st, d, A, red);
+  vi::launch_s0(c->st, d, A, red, c->prm.wide_pass_max);
   A.evals = ev_pass;
   prof_end(c, r, VI_K_INIT, level, nS);
   VI_TRY(launched("s0"));

@@ -166,7 +166,10 @@ void launch_fill_u64(hipStream_t st, unsigned long long* p, int32_t n);
 
 // red: compare the reduced distance (unmasked searches of a level with
 // features); launch_rerank then evaluates every target's match exactly
-void launch_s0(hipStream_t st, DevLevel L, const PassArgs& A, bool red = false);
+// wide_max as for launch_pass: step 0 of lists up to that size takes the group
+// form
+void launch_s0(hipStream_t st, DevLevel L, const PassArgs& A, bool red = false,
+               int32_t wide_max = -1);
 // Whether launch_pass takes the wide form for a target list of nS targets:
 // exact passes (also the onion peel's masked ones) over at most wide_max
 // targets (-1: the library's limit).

@@ -555,6 +555,17 @@ __device__ __forceinline__ void store_match(const DevLevel& L, const PassArgs& A
   }
 }
 
+// Target lists up to this size take the wide pass (kWideTargets targets per
+// workgroup of kBlock lanes).  Larger ones take the one-lane pass: with its
+// 76 registers six of its workgroups (1536 targets) are resident per compute
+// unit against four of the wide pass's (256 targets), and its early exit
+// costs fewer loads, so once the targets fill the device it is faster
+// (measured crossover between 72 k and 220 k targets).
+constexpr int32_t kWideMaxTargets = 131072;
+constexpr int kWideTargets = 64;
+// Step 0's target lists up to this size take the group form as well.
+constexpr int32_t kWideS0MaxTargets = 131072;
+
 constexpr int kGrp = 8;
 // Unmasked exact passes without random search over the larger lists: a
 // workgroup of 256 targets whose queue holds at most this many candidates
@@ -606,7 +617,8 @@ __device__ __forceinline__ uint32_t group_sum8(uint32_t d) {
 template <int SA, int SB, bool MASKED>
 __device__ __forceinline__ uint32_t group_rows(const DevLevel& L, const uint8_t* __restrict__ excl,
                                                int32_t p, int32_t py, int32_t pt, int32_t c,
-                                               int lg, uint32_t xm, bool vid) {
+                                               int lg, uint32_t xm, bool vid,
+                                               uint32_t* nvox = nullptr) {
   constexpr int NS = SB < 0 ? 1 : 2;
   const uint2* __restrict__ vox = L.vox;
   Row5 a[NS], b[NS];
@@ -660,6 +672,13 @@ __device__ __forceinline__ uint32_t group_rows(const DevLevel& L, const uint8_t*
       acc_voxel(q, ok ? a[i].v[x] : make_uint2(0, 0), ok ? b[i].v[x] : make_uint2(0, 0));
     }
   }
+  // the voxels compared, summed over the group
+  if (nvox) {
+    uint32_t n = 0;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) n += __builtin_popcount(okm[i]);
+    *nvox = group_sum8(n);
+  }
   return group_sum8(q.sc + (uint32_t)L.lambda * q.st);
 }
 
@@ -674,6 +693,24 @@ __device__ __forceinline__ uint32_t group_ssd(const DevLevel& L, const uint8_t* 
   const uint32_t d0 = group_rows<0, 3, MASKED>(L, excl, p, py, pt, c, lg, xm, vid);
   if (!vid || d0 > abort_above) return d0;
   return d0 + group_rows<1, 2, MASKED>(L, excl, p, py, pt, c, lg, xm, true);
+}
+
+// The full distance (no early exit) and the number of voxels compared, by
+// the kGrp lanes of a group, every row load of a video patch in flight at
+// once.
+template <bool MASKED>
+__device__ __forceinline__ uint32_t group_full(const DevLevel& L, const uint8_t* excl, int32_t p,
+                                               int32_t px, int32_t py, int32_t pt, int32_t c,
+                                               int lg, uint32_t& nvox) {
+  const bool vid = L.ht != 0;
+  const int klo = px < 2 ? 2 - px : 0;
+  const int khi = px + 2 >= L.W ? L.W + 1 - px : 4;
+  const uint32_t xm = (0x1fu << klo) & (0x1fu >> (4 - khi));
+  uint32_t n0, n1 = 0;
+  uint32_t d = group_rows<0, 3, MASKED>(L, excl, p, py, pt, c, lg, xm, vid, &n0);
+  if (vid) d += group_rows<1, 2, MASKED>(L, excl, p, py, pt, c, lg, xm, true, &n1);
+  nvox = n0 + n1;
+  return d;
 }
 
 // One block of BLK consecutive targets (block index blk of the target list);
@@ -907,6 +944,67 @@ __global__ __launch_bounds__(kBlock) void k_pass_wide(DevLevel L, PassArgs A) {
   __shared__ WideShared<TB> sh;
   const int ne = pass_block_wide<TB, MASKED>(L, A, xcd_block(blockIdx.x, gridDim.x), sh);
   count_evals(A.evals, ne);
+}
+
+// Step 0 for small target lists: kWideTargets targets per workgroup of
+// kBlock lanes, each target's distance by a group of kGrp lanes (the same
+// random initialisation, distance, count and marks as s0_target).
+template <bool MASKED>
+__global__ __launch_bounds__(kBlock) void k_s0_wide(DevLevel L, PassArgs A) {
+  constexpr int TB = kWideTargets;
+  __shared__ int32_t s_p[TB], s_xy[TB], s_t[TB], s_c[TB];
+  __shared__ uint32_t s_d[TB], s_n[TB];
+  const int tid = threadIdx.x;
+  const bool tgt = tid < TB;  // wave-uniform
+  const int32_t i = xcd_block(blockIdx.x, gridDim.x) * TB + tid;
+  const bool active = tgt && i < A.nS;
+  int2* nnf = const_cast<int2*>(A.nin);
+  int32_t p = 0, px = 0, py = 0, pt = 0, c = -1;
+  int2 old = make_int2(0, 0);
+  uint8_t n_old = 0;
+  if (active) {
+    p = A.tlist[i];
+    unlin(L, p, px, py, pt);
+    old = nnf[p];
+    n_old = L.nvox[p];
+    c = old.x;
+    if (c < 0 || c >= L.V || !L.dsrc[c]) {
+      uint64_t w[4];
+      philox4x64_10((uint64_t)p, A.step, 0, ((uint64_t)L.level << 8) | 1u, L.seed, 0, w);
+      c = L.dlist[draw_below(w[0], (uint32_t)L.nD)];
+    }
+  }
+  if (tgt) {
+    s_p[tid] = p;
+    s_xy[tid] = px | (py << 16);
+    s_t[tid] = pt;
+    s_c[tid] = active ? c : -1;
+  }
+  __syncthreads();
+  const int g = tid / kGrp, lg = tid % kGrp;
+  for (int e = g; e < TB; e += kBlock / kGrp) {
+    const int32_t ce = s_c[e];
+    if (ce >= 0) {
+      const int32_t xy = s_xy[e];
+      uint32_t n;
+      const uint32_t d =
+          group_full<MASKED>(L, A.excl, s_p[e], xy & 0xFFFF, xy >> 16, s_t[e], ce, lg, n);
+      if (lg == 0) {
+        s_d[e] = d;
+        s_n[e] = n;
+      }
+    }
+  }
+  __syncthreads();
+  if (active) {
+    const uint32_t d = s_d[tid];
+    const uint8_t n = (uint8_t)s_n[tid];
+    nnf[p] = make_int2(c, (int32_t)d);
+    L.nvox[p] = n;
+    L.chg[p] = 0;
+    if (c != old.x || (int32_t)d != old.y || n != n_old) L.rmark[p] = (uint8_t)L.repoch;
+  }
+  count_evals(A.evals, active ? 1 : 0);
 }
 
 __global__ void k_copy_targets(const int32_t* tlist, int32_t nS, const int2* src, int2* dst) {
@@ -1729,14 +1827,6 @@ __global__ void k_out_rgb(DevLevel L, uint8_t* out) {
 // ------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------
-// Target lists up to this size take the wide pass (kWideTargets targets per
-// workgroup of kBlock lanes).  Larger ones take the one-lane pass: with its
-// 76 registers six of its workgroups (1536 targets) are resident per compute
-// unit against four of the wide pass's (256 targets), and its early exit
-// costs fewer loads, so once the targets fill the device it is faster
-// (measured crossover between 72 k and 220 k targets).
-static constexpr int32_t kWideMaxTargets = 131072;
-static constexpr int kWideTargets = 64;
 
 static inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
 
@@ -1778,9 +1868,15 @@ void launch_fill_u64(hipStream_t st, unsigned long long* p, int32_t n) {
   k_fill_u64<<<grid_for(n), kBlock, 0, st>>>(p, n);
 }
 
-void launch_s0(hipStream_t st, DevLevel L, const PassArgs& A, bool red) {
+void launch_s0(hipStream_t st, DevLevel L, const PassArgs& A, bool red, int32_t wide_max) {
   if (A.nS <= 0) return;
-  if (A.excl)
+  const bool wide = !red && A.nS <= (wide_max < 0 ? kWideS0MaxTargets : wide_max);
+  const unsigned wide_grid = (unsigned)((A.nS + kWideTargets - 1) / kWideTargets);
+  if (wide && A.excl)
+    k_s0_wide<true><<<wide_grid, kBlock, 0, st>>>(L, A);
+  else if (wide)
+    k_s0_wide<false><<<wide_grid, kBlock, 0, st>>>(L, A);
+  else if (A.excl)
     k_s0<true, false><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
   else if (red)
     k_s0<false, true><<<grid_for(A.nS), kBlock, 0, st>>>(L, A);
