@@ -48,6 +48,10 @@ def test_params_default_and_validation_on_host(libvi):
     from paper_1503_05528_amd import vi
     p = vi.default_params()
     assert (p.lambda_, p.pm_iters, p.n_jf, list(p.jf_steps)[:3]) == (50, 10, 3, [4, 2, 1])
+    # the pass form is the library's choice unless set; below -1 is refused
+    assert p.wide_pass_max == -1 and p.reduce_dims == 0
+    assert vi.footprint_bytes(vi.default_params(wide_pass_max=0), 854, 480, 100, 0.05) > 0
+    assert vi.footprint_bytes(vi.default_params(wide_pass_max=-2), 854, 480, 100, 0.05) == 0
     assert vi.footprint_bytes(p, 854, 480, 100, 0.05) > 854 * 480 * 100 * 36
     bad = vi.default_params(patch=(3, 3, 3))
     assert vi.footprint_bytes(bad, 854, 480, 100, 0.05) == 0
