@@ -402,10 +402,12 @@ __device__ __forceinline__ int lane_prefix(uint64_t mask) {
 // A workgroup of 256 targets works in three phases: (1) each thread gathers
 // its target's candidates and appends (target, direction) entries to an LDS
 // queue, grouped per wave and direction so that neighbouring entries point
-// at neighbouring voxels; (2) all threads evaluate the queue densely and
-// fold (distance << 3 | index) into the target's LDS minimum with a 64-bit
-// atomic min, which is exactly the lexicographic (distance, index) order;
-// (3) each thread takes its target's winner and runs the random search.
+// at neighbouring voxels; (2) all threads evaluate the queue densely (one
+// lane per entry; in the GQ instantiation a short queue takes one group of
+// kGrp lanes per entry) and fold (distance << 3 | index) into the target's
+// LDS minimum with a 64-bit atomic min, which is exactly the lexicographic
+// (distance, index) order; (3) each thread takes its target's winner and
+// runs the random search.
 // ------------------------------------------------------------------------
 template <int BLK>
 struct PassShared {
@@ -765,20 +767,22 @@ __device__ __forceinline__ int pass_block(const DevLevel& L, const PassArgs& A, 
         if (lg == 0 && d <= bound)
           atomicMin(&s_best[lt], ((unsigned long long)d << 3) | (unsigned long long)(j + 1));
       }
-    } else
-    for (int32_t e = tid; e < nq; e += BLK) {
-      const uint32_t ent = s_q[e];
-      const int lt = ent & 255, j = ent >> 8;
-      const int32_t xy = s_xy[lt];
-      // a candidate whose partial distance exceeds the current best cannot win
-      const uint32_t bound = (uint32_t)(s_best[lt] >> 3);
-      int32_t n;
-      const uint32_t d =
-          RED ? red_dist(L, s_p[lt], s_cand[lt * 6 + j])
-              : patch_ssd<MASKED, true>(L, A.excl, s_p[lt], xy & 0xFFFF, xy >> 16, s_t[lt],
-                                        s_cand[lt * 6 + j], bound, n);
-      if (d <= bound)
-        atomicMin(&s_best[lt], ((unsigned long long)d << 3) | (unsigned long long)(j + 1));
+    } else {
+      // one lane per candidate, with early exit
+      for (int32_t e = tid; e < nq; e += BLK) {
+        const uint32_t ent = s_q[e];
+        const int lt = ent & 255, j = ent >> 8;
+        const int32_t xy = s_xy[lt];
+        // a candidate whose partial distance exceeds the current best cannot win
+        const uint32_t bound = (uint32_t)(s_best[lt] >> 3);
+        int32_t n;
+        const uint32_t d =
+            RED ? red_dist(L, s_p[lt], s_cand[lt * 6 + j])
+                : patch_ssd<MASKED, true>(L, A.excl, s_p[lt], xy & 0xFFFF, xy >> 16, s_t[lt],
+                                          s_cand[lt * 6 + j], bound, n);
+        if (d <= bound)
+          atomicMin(&s_best[lt], ((unsigned long long)d << 3) | (unsigned long long)(j + 1));
+      }
     }
     if (tid == 0) ne += nq;
     __syncthreads();
