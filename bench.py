@@ -935,7 +935,7 @@ def measure_plain(config, steps, warmup, em_iters, temporal=False, reduce_dims=0
     pass_wide = None
     if wide:
         pass_wide = {
-            "kernel": "k_pass_wide<64> (the same pass on small target lists, eight lanes per "
+            "kernel": "k_pass_wide<64, false> (the same pass on small target lists, eight lanes per "
                       "distance)",
             "launches_per_step": wide["launches"], "ms_per_step": round(wide["ms"], 3),
             "avg_launch_ms": round(wide["ms"] / wide["launches"], 5),
