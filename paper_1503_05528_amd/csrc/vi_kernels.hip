@@ -1636,17 +1636,26 @@ __global__ void k_grad(const uint8_t* __restrict__ rgb, DevLevel L, uint32_t* __
   gpk[i] = out;
 }
 
-// sums over [x, x+s) of the defined derivatives: .x = gx sum | count << 20
-__global__ void k_box_h(const uint32_t* __restrict__ gpk, DevLevel L, int32_t s,
-                        uint2* __restrict__ hsum) {
-  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= L.V) return;
-  int32_t x, y, t;
-  unlin(L, i, x, y, t);
+// sums over [x, x+s) of the defined derivatives: .x = gx sum | count << 20.
+// A workgroup takes kBlock consecutive x of one row (y, t) and stages the
+// row's entries [x0, x0 + kBlock + s - 1) in LDS (entries past the row read
+// 0: no defined derivative), so each entry is fetched once instead of s
+// times.  s <= kMaxBox (2^(levels - 1), levels <= 8).
+constexpr int32_t kMaxBox = 128;
+__global__ __launch_bounds__(kBlock) void k_box_h(const uint32_t* __restrict__ gpk, DevLevel L,
+                                                  int32_t s, uint2* __restrict__ hsum) {
+  __shared__ uint32_t seg[kBlock + kMaxBox];
+  const int32_t nseg = (L.W + kBlock - 1) / kBlock;
+  const int32_t row = blockIdx.x / nseg, x0 = (blockIdx.x % nseg) * kBlock;
+  const uint32_t* __restrict__ src = gpk + (size_t)row * L.W;
+  for (int32_t k = threadIdx.x; k < kBlock + s - 1; k += kBlock)
+    seg[k] = x0 + k < L.W ? src[x0 + k] : 0u;
+  __syncthreads();
+  const int32_t x = x0 + (int32_t)threadIdx.x;
+  if (x >= L.W) return;
   uint32_t sx = 0, cx = 0, sy = 0, cy = 0;
-  const int32_t e = min(L.W, x + s);
-  for (int32_t xx = x; xx < e; ++xx) {
-    const uint32_t g = gpk[i + (xx - x)];
+  for (int32_t k = 0; k < s; ++k) {
+    const uint32_t g = seg[threadIdx.x + k];
     if (g & (1u << 10)) {
       sx += g & 1023u;
       ++cx;
@@ -1656,35 +1665,73 @@ __global__ void k_box_h(const uint32_t* __restrict__ gpk, DevLevel L, int32_t s,
       ++cy;
     }
   }
-  hsum[i] = make_uint2(sx | (cx << 20), sy | (cy << 20));
+  hsum[(size_t)row * L.W + x] = make_uint2(sx | (cx << 20), sy | (cy << 20));
 }
 
-// texture of level l: T(2^l X, 2^l Y, t) of the finest level, rounded half up
-// mean of |grey difference| = S / (3c); zero inside the level's hole
+// texture of level l: T(2^l X, 2^l Y, t) of the finest level (or 2^l t as
+// well when the pyramid subsamples time), rounded half up mean of |grey
+// difference| = S / (3c) over the sums of the finest level's rows
+// [2^l Y, min(H, 2^l Y + s)) at column 2^l X; zero inside the level's hole.
+// A thread takes kTexRun consecutive rows Y of one column (X, t) and slides
+// the window: consecutive windows are 2^l rows apart, so while 2^l < s it
+// drops 2^l rows and adds 2^l (4 loads per output at level 1 instead of s =
+// 16), and from 2^l >= s on it sums each window afresh.  Thread order: X
+// fastest.  The sums stay below 2^25 (s <= 128 rows of at most 128 x 1023),
+// so 32-bit arithmetic is exact.
+constexpr int32_t kTexRun = 32;
+
+struct TexSums {
+  uint32_t sx = 0, cx = 0, sy = 0, cy = 0;
+  __device__ __forceinline__ void add(uint2 h) {
+    sx += h.x & 0xFFFFFu;
+    cx += h.x >> 20;
+    sy += h.y & 0xFFFFFu;
+    cy += h.y >> 20;
+  }
+  __device__ __forceinline__ void sub(uint2 h) {
+    sx -= h.x & 0xFFFFFu;
+    cx -= h.x >> 20;
+    sy -= h.y & 0xFFFFFu;
+    cy -= h.y >> 20;
+  }
+};
+
 __global__ void k_tex_level(const uint2* __restrict__ hsum, DevLevel L0, DevLevel Ll, int32_t l,
                             int32_t s) {
-  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= Ll.V) return;
-  uint32_t tx = 0, ty = 0;
-  if (!Ll.hole[i]) {
-    int32_t X, Y, tl;
-    unlin(Ll, i, X, Y, tl);
-    // the finest level's features at (2^l x, 2^l y, t), or 2^l t as well
-    // when the pyramid subsamples time
-    const int32_t x = X << l, y = Y << l, t = Ll.T != L0.T ? tl << l : tl;
-    uint64_t sx = 0, cx = 0, sy = 0, cy = 0;
-    const int32_t e = min(L0.H, y + s);
-    for (int32_t yy = y; yy < e; ++yy) {
-      const uint2 h = hsum[(t * L0.H + yy) * L0.W + x];
-      sx += h.x & 0xFFFFFu;
-      cx += h.x >> 20;
-      sy += h.y & 0xFFFFFu;
-      cy += h.y >> 20;
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int32_t runs = (Ll.H + kTexRun - 1) / kTexRun;
+  const int32_t X = (int32_t)(gid % Ll.W);
+  const int64_t rt = gid / Ll.W;
+  const int32_t run = (int32_t)(rt % runs), tl = (int32_t)(rt / runs);
+  if (tl >= Ll.T) return;
+  const int32_t H0 = L0.H, step = 1 << l;
+  const int32_t t = Ll.T != L0.T ? tl << l : tl;
+  const uint2* __restrict__ col = hsum + (size_t)t * H0 * L0.W + ((size_t)X << l);
+  const int32_t Y0 = run * kTexRun, Y1 = min(Ll.H, Y0 + kTexRun);
+  TexSums w;
+  for (int32_t yy = Y0 * step; yy < min(H0, Y0 * step + s); ++yy) w.add(col[(size_t)yy * L0.W]);
+  for (int32_t Y = Y0; Y < Y1; ++Y) {
+    const int32_t i = (tl * Ll.H + Y) * Ll.W + X;
+    uint32_t tx = 0, ty = 0;
+    if (!Ll.hole[i]) {
+      tx = w.cx ? (2 * w.sx + 3 * w.cx) / (6 * w.cx) : 0;
+      ty = w.cy ? (2 * w.sy + 3 * w.cy) / (6 * w.cy) : 0;
     }
-    tx = cx ? (uint32_t)((2 * sx + 3 * cx) / (6 * cx)) : 0;
-    ty = cy ? (uint32_t)((2 * sy + 3 * cy) / (6 * cy)) : 0;
+    Ll.vox[i].y = tx | (ty << 8);
+    if (Y + 1 == Y1) break;
+    // the window of Y + 1: [y + step, min(H0, y + step + s))
+    const int32_t y = Y * step;
+    if (step < s) {
+      for (int32_t yy = y; yy < y + step; ++yy)
+        if (yy < H0) w.sub(col[(size_t)yy * L0.W]);
+      for (int32_t yy = y + s; yy < y + s + step; ++yy)
+        if (yy < H0) w.add(col[(size_t)yy * L0.W]);
+    } else {
+      w = TexSums();
+      for (int32_t yy = y + step; yy < min(H0, y + step + s); ++yy)
+        w.add(col[(size_t)yy * L0.W]);
+    }
   }
-  Ll.vox[i].y = tx | (ty << 8);
 }
 
 // ------------------------------------------------------------------------
@@ -1845,12 +1892,14 @@ void launch_pyr_down(hipStream_t st, DevLevel F, DevLevel C) {
 void launch_texture(hipStream_t st, const uint8_t* rgb, DevLevel L0, int32_t s, uint32_t* gpk,
                     uint2* hsum) {
   k_grad<<<grid_for(L0.V), kBlock, 0, st>>>(rgb, L0, gpk);
-  k_box_h<<<grid_for(L0.V), kBlock, 0, st>>>(gpk, L0, s, hsum);
+  const int64_t nseg = (L0.W + kBlock - 1) / kBlock;
+  k_box_h<<<(unsigned)(nseg * L0.H * L0.T), kBlock, 0, st>>>(gpk, L0, s, hsum);
 }
 
 void launch_texture_level(hipStream_t st, const uint2* hsum, DevLevel L0, DevLevel Ll, int32_t l,
                           int32_t s) {
-  k_tex_level<<<grid_for(Ll.V), kBlock, 0, st>>>(hsum, L0, Ll, l, s);
+  const int64_t n = (int64_t)Ll.W * ((Ll.H + kTexRun - 1) / kTexRun) * Ll.T;
+  k_tex_level<<<grid_for(n), kBlock, 0, st>>>(hsum, L0, Ll, l, s);
 }
 
 void launch_dilate5(hipStream_t st, const uint8_t* src, uint8_t* dst, uint8_t* tmp1,
