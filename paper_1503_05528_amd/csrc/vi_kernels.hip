@@ -560,9 +560,9 @@ __device__ __forceinline__ void store_match(const DevLevel& L, const PassArgs& A
 // Target lists up to this size take the wide pass (kWideTargets targets per
 // workgroup of kBlock lanes).  Larger ones take the one-lane pass: with its
 // 76 registers six of its workgroups (1536 targets) are resident per compute
-// unit against four of the wide pass's (256 targets), and its early exit
-// costs fewer loads, so once the targets fill the device it is faster
-// (measured crossover between 72 k and 220 k targets).
+// unit against five of the wide pass's (320 targets, 83 registers), and its
+// early exit costs fewer loads, so once the targets fill the device it is
+// faster (measured crossover between 72 k and 220 k targets).
 constexpr int32_t kWideMaxTargets = 131072;
 constexpr int kWideTargets = 64;
 // Step 0's target lists up to this size take the group form as well.
