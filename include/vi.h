@@ -225,6 +225,16 @@ size_t vi_ctx_bytes(const vi_ctx* ctx);
  * memory of the current device and returns the bytes freed. */
 size_t vi_pool_trim(void);
 
+/* Failure injection, for tests of the library's error handling (callers
+ * that must see an exhausted device handled cleanly): after this call the
+ * next n device allocations of contexts (the memory pool above) succeed and
+ * every later one fails as an exhausted device would, so that the call
+ * needing it returns VI_E_NOMEM; n < 0 turns the injection off.  Returns
+ * the bytes of pool blocks held by live contexts at the time of the call,
+ * so that a test can check that a failed call released what it took.
+ * Process-wide; not for production use. */
+int64_t vi_debug_fail_allocs(int64_t n);
+
 /* Rebinds the context to another stream (hipStream_t or NULL). */
 vi_status vi_set_stream(vi_ctx* ctx, void* hip_stream);
 

@@ -12,6 +12,7 @@
 // stream.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -70,9 +71,23 @@ size_t trim_locked(DevPool& d, std::vector<void*>& out) {
   return n;
 }
 
+// Failure injection for the tests of the error paths: -1 = off; n >= 0 =
+// the next n allocations succeed, every later one fails.
+std::atomic<int64_t> g_fail_after{-1};
+
+bool forced_failure() {
+  int64_t v = g_fail_after.load();
+  while (v >= 0) {
+    if (v == 0) return true;
+    if (g_fail_after.compare_exchange_weak(v, v - 1)) return false;
+  }
+  return false;
+}
+
 }  // namespace
 
 void* pool_alloc(int dev, size_t bytes) {
+  if (forced_failure()) return nullptr;
   Pool& P = pool();
   const size_t cls = size_class(bytes ? bytes : 1);
   {
@@ -175,4 +190,15 @@ extern "C" size_t vi_pool_trim(void) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   return vi::pool_trim(dev);
+}
+
+extern "C" int64_t vi_debug_fail_allocs(int64_t n) {
+  vi::Pool& P = vi::pool();
+  int64_t live = 0;
+  {
+    std::lock_guard<std::mutex> g(P.mu);
+    for (const auto& kv : P.live) live += (int64_t)kv.second;
+  }
+  vi::g_fail_after.store(n < 0 ? -1 : n);
+  return live;
 }

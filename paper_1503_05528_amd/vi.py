@@ -70,6 +70,7 @@ SIGNATURES = {
     "vi_closer_than_constant": (_i32, [_vp, _i32, _vp, _i32, _i32, _i32, _i32, _i32, _i32,
                                        _i32, _vp, _vp]),
     "vi_params_default": (_i32, [C.c_void_p]),
+    "vi_debug_fail_allocs": (_i64, [_i64]),
     "vi_create": (_i32, [C.POINTER(_vp), C.c_void_p, _i32, _i32, _i32, _vp, _vp, _vp]),
     "vi_level_info": (_i32, [_vp, _i32, C.POINTER(_i32), C.POINTER(_i64)]),
     "vi_level_sets": (_i32, [_vp, _i32, _vp, _vp, _vp]),
@@ -184,6 +185,13 @@ def pool_trim() -> int:
     """Frees the device memory libvi keeps from destroyed contexts (current
     device); returns the bytes freed."""
     return int(lib().vi_pool_trim())
+
+
+def fail_allocs(n: int) -> int:
+    """Failure injection for tests: the next n context allocations succeed,
+    later ones fail (n < 0: off).  Returns the pool bytes held by live
+    contexts."""
+    return int(lib().vi_debug_fail_allocs(int(n)))
 
 
 class Clip:
